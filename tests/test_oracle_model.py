@@ -1,0 +1,181 @@
+"""Pins of the oracle's vehicle model and running / terminal costs.
+
+Dynamics F (Eq. 1; reading: rear-axle kinematic bicycle, forward Euler) are
+pinned by closed forms of straight, constant-acceleration and constant-steering
+motion.  The track terms of Eq. 20-21 (reading: Sampson signed distance to an
+elliptic centreline) are pinned on the circle, where the Sampson distance has a
+closed form, and to first order near any ellipse.  The obstacle cost (Eq. 22)
+is pinned on hand-placed discs, the boundary cost (Eq. 21) at known values and
+the terminal cost (Eq. 23) by the arc length of a circle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_12842_amd import workloads as W
+
+
+def _roll(x0, u, n, dt=0.05, wb=2.5):
+    xs = [np.asarray(x0, dtype=np.float64)]
+    for _ in range(n):
+        xs.append(oracle.dynamics(xs[-1], u, dt, wb))
+    return np.array(xs)
+
+
+def test_straight_line():
+    x0 = [3.0, -2.0, 0.7, 4.0]
+    xs = _roll(x0, [0.0, 0.0], 50)
+    t = np.arange(51)
+    np.testing.assert_allclose(xs[:, 0], 3.0 + t * 0.05 * 4.0 * math.cos(0.7), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(xs[:, 1], -2.0 + t * 0.05 * 4.0 * math.sin(0.7), rtol=0, atol=1e-12)
+    assert np.all(xs[:, 2] == 0.7) and np.all(xs[:, 3] == 4.0)
+
+
+def test_constant_acceleration():
+    a, dt, v0, psi = 1.5, 0.05, 2.0, -0.3
+    xs = _roll([0.0, 0.0, psi, v0], [a, 0.0], 40, dt=dt)
+    t = np.arange(41)
+    np.testing.assert_allclose(xs[:, 3], v0 + t * a * dt, rtol=0, atol=1e-12)
+    # x_t = x_0 + dt cos(psi) sum_{j<t} v_j
+    s = dt * (t * v0 + a * dt * t * (t - 1) / 2.0)
+    np.testing.assert_allclose(xs[:, 0], s * math.cos(psi), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(xs[:, 1], s * math.sin(psi), rtol=0, atol=1e-12)
+
+
+def test_constant_steering_is_a_polygon_on_a_circle():
+    dt, wb, v, delta, psi0 = 0.05, 2.5, 6.0, 0.3, 0.4
+    n = 60
+    xs = _roll([1.0, 2.0, psi0, v], [0.0, delta], n, dt=dt, wb=wb)
+    D = dt * v * math.tan(delta) / wb
+    t = np.arange(n + 1)
+    np.testing.assert_allclose(xs[:, 2], psi0 + t * D, rtol=0, atol=1e-12)
+    # x_t = x_0 + dt v sum_{j<t} cos(psi0 + j D)  (Lagrange's trigonometric sum)
+    half = np.sin(t * D / 2.0) / math.sin(D / 2.0)
+    mid = psi0 + (t - 1) * D / 2.0
+    np.testing.assert_allclose(xs[:, 0], 1.0 + dt * v * half * np.cos(mid), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(xs[:, 1], 2.0 + dt * v * half * np.sin(mid), rtol=0, atol=1e-11)
+
+
+def _circle_params(R, ox=0.0, oy=0.0, hw=1.0, **kw):
+    p = dict(W.PRESETS["c1"])
+    p.update(track=(ox, oy, R, R, hw))
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("R", [4.0, 10.0, 50.0])
+def test_sampson_distance_on_a_circle(R):
+    # for a circle, G = rho^2/R^2 - 1 and |grad G| = 2 rho / R^2, so
+    # e = (rho^2 - R^2) / (2 rho)
+    p = _circle_params(R, ox=1.5, oy=-0.5, hw=2.0)
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        rho = rng.uniform(0.3 * R, 1.7 * R)
+        th = rng.uniform(-math.pi, math.pi)
+        x = [1.5 + rho * math.cos(th), -0.5 + rho * math.sin(th), 0.0, 1.0]
+        e, d = oracle.track_terms(p, x)
+        ref = (rho * rho - R * R) / (2 * rho)
+        assert e == pytest.approx(ref, rel=1e-12, abs=1e-12)
+        assert d == pytest.approx(2.0 - abs(ref), rel=1e-12, abs=1e-12)
+
+
+def test_sampson_distance_on_and_near_an_ellipse():
+    a, b = 50.0, 20.0
+    p = dict(W.PRESETS["c2"])
+    p.update(track=(0.0, 0.0, a, b, 3.0))
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        th = rng.uniform(-math.pi, math.pi)
+        cx, cy = a * math.cos(th), b * math.sin(th)
+        e, d = oracle.track_terms(p, [cx, cy, 0.0, 0.0])
+        assert abs(e) < 1e-12 and d == pytest.approx(3.0, abs=1e-12)
+        # a point s metres along the outward unit normal: e = s + O(s^2)
+        nx, ny = math.cos(th) / a, math.sin(th) / b
+        nn = math.hypot(nx, ny)
+        for s in (1e-3, -1e-3):
+            e, _ = oracle.track_terms(p, [cx + s * nx / nn, cy + s * ny / nn, 0.0, 0.0])
+            assert abs(e - s) < 1e-5 * abs(s) * 100, (th, s, e)
+            assert np.sign(e) == np.sign(s)
+
+
+def test_boundary_cost_values():
+    assert oracle.boundary_cost(0.0) == pytest.approx(0.5, abs=1e-15)
+    assert oracle.boundary_cost(0.01) == pytest.approx(0.25, abs=1e-15)     # atan(-1)/pi + 1/2
+    assert oracle.boundary_cost(-0.01) == pytest.approx(0.75, abs=1e-15)
+    assert oracle.boundary_cost(1e6) < 1e-7
+    assert oracle.boundary_cost(-1e6) > 1 - 1e-7
+    ds = np.linspace(-1, 1, 201)
+    vals = np.array([oracle.boundary_cost(d) for d in ds])
+    assert np.all(np.diff(vals) < 0) and np.all((vals >= 0) & (vals <= 1))
+
+
+def test_obstacle_count_strict_and_summed():
+    obs = [[0.0, 0.0, 1.0], [0.5, 0.0, 1.0], [10.0, 10.0, 0.5]]
+    assert oracle.obstacle_count(obs, 0.2, 0.0) == 2       # inside two overlapping discs
+    assert oracle.obstacle_count(obs, 1.0, 0.0) == 1       # on the first boundary: not inside (strict)
+    assert oracle.obstacle_count(obs, 1.5, 0.0) == 0       # on the second boundary
+    assert oracle.obstacle_count(obs, 10.0, 10.4) == 1
+    assert oracle.obstacle_count(obs, 3.0, 3.0) == 0
+    assert oracle.obstacle_count(np.zeros((0, 3)), 0.0, 0.0) == 0
+    assert oracle.obstacle_margin(obs, 3.0, 0.0) == pytest.approx(1.5, abs=1e-15)
+
+
+def test_running_cost_terms_separately():
+    R = 10.0
+    obs = [[0.0, 10.0, 1.0]]
+    x = [0.0, 10.3, 0.0, 7.0]      # inside the obstacle, 0.3 m outside the circle
+    base = dict(c_bdry=0.0, c_obs=0.0, c_dev=0.0, c_v=0.0, v_ref=5.0)
+    e = (10.3 ** 2 - R * R) / (2 * 10.3)
+    p = _circle_params(R, hw=1.0, **dict(base, c_obs=1.0))
+    assert oracle.running_cost(p, obs, x) == 1.0
+    p = _circle_params(R, hw=1.0, **dict(base, c_v=1.0))
+    assert oracle.running_cost(p, obs, x) == pytest.approx(4.0, abs=1e-14)
+    p = _circle_params(R, hw=1.0, **dict(base, c_dev=1.0))
+    assert oracle.running_cost(p, obs, x) == pytest.approx(e * e, rel=1e-12)
+    p = _circle_params(R, hw=1.0, **dict(base, c_bdry=1.0))
+    d = 1.0 - abs(e)
+    assert oracle.running_cost(p, obs, x) == pytest.approx(math.atan(-100 * d) / math.pi + 0.5, rel=1e-12)
+    # weights add linearly
+    p = _circle_params(R, hw=1.0, c_bdry=2.0, c_obs=3.0, c_dev=5.0, c_v=7.0, v_ref=5.0)
+    ref = 2.0 * (math.atan(-100 * d) / math.pi + 0.5) + 3.0 + 5.0 * e * e + 7.0 * 4.0
+    assert oracle.running_cost(p, obs, x) == pytest.approx(ref, rel=1e-12)
+
+
+def test_running_cost_translation_invariant():
+    # moving the track, the obstacles and the vehicle by the same vector leaves q unchanged
+    w = W.make_world("c2")
+    p = dict(w["params"], c_bdry=1.0)
+    obs = w["obstacles"].astype(np.float64)
+    rng = np.random.default_rng(2)
+    for _ in range(30):
+        x = [rng.uniform(-55, 55), rng.uniform(-25, 25), 0.3, rng.uniform(0, 10)]
+        # place some points right next to obstacles too
+        j = rng.integers(len(obs))
+        x2 = [obs[j, 0] + 0.2, obs[j, 1] - 0.1, 0.0, 3.0]
+        for xx in (x, x2):
+            q0 = oracle.running_cost(p, obs, xx)
+            sh = np.array([7.25, -3.5])
+            pt = dict(p, track=(p["track"][0] + sh[0], p["track"][1] + sh[1]) + tuple(p["track"][2:]))
+            ob = obs.copy()
+            ob[:, :2] += sh
+            q1 = oracle.running_cost(pt, ob, [xx[0] + sh[0], xx[1] + sh[1], xx[2], xx[3]])
+            assert q1 == pytest.approx(q0, rel=1e-9, abs=1e-9)
+
+
+def test_terminal_cost_is_arc_length_on_a_circle():
+    R = 8.0
+    p = _circle_params(R, c4=0.6, c5=2.0)
+    x0 = [R, 0.0, math.pi / 2, 1.0]
+    for th in (0.1, math.pi / 2, 2.0, -1.0):
+        x = [R * math.cos(th), R * math.sin(th), 0.0, 0.0]
+        assert oracle.progress(p, x0, x) == pytest.approx(R * th, rel=1e-12)
+        c4 = float(np.float32(0.6))  # parameters are float32 values
+        assert oracle.terminal_cost(p, x0, x) == pytest.approx(c4 - 2.0 * R * th, rel=1e-12)
+    # the progress is wrapped to (-pi, pi]: exactly half a lap counts as +pi R
+    x = [-R, 0.0, 0.0, 0.0]
+    assert oracle.progress(p, x0, x) == pytest.approx(math.pi * R, rel=1e-12)
+    th = math.pi + 0.1
+    x = [R * math.cos(th), R * math.sin(th), 0.0, 0.0]
+    assert oracle.progress(p, x0, x) == pytest.approx(R * (th - 2 * math.pi), rel=1e-12)
