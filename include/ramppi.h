@@ -1,0 +1,177 @@
+/*
+ * ramppi.h - C ABI of the MI355X (gfx950) Risk-Aware MPPI control step.
+ *
+ * The library computes one iteration of Risk-Aware Model Predictive Path
+ * Integral control (Yin, Zhang, Tsiotras, arXiv 2209.12842, Algorithm 1):
+ * K control sequences are sampled around the mean sequence V (Eq. 2b-2c), each
+ * is rolled through the nominal model (Eq. 1) for its cost S (Eq. 3) and
+ * through M disturbed models (Eq. 6) for the risk costs L (Eq. 9); the
+ * per-sample CVaR of the scaled risk costs (Eq. 10-13, 18-19) adds the
+ * violation cost (Eq. 14-16), and the path-integral weights (Eq. 17) give the
+ * new sequence V+ as the weighted average of the sampled sequences (Eq. 4).
+ *
+ * Notation: K samples (the paper's M), T horizon steps (the paper's K), M
+ * disturbance draws per sample (the paper's N).  Vehicle model: kinematic
+ * bicycle with state (x, y, psi, v) and control (acceleration, steering).
+ *
+ * Memory: the caller owns every device buffer (the workspace, V, the stage
+ * buffers) and every stream; the library owns only the host-side handle and a
+ * small pinned host buffer for the first command.  Pointers named *_dev are
+ * device pointers, *_host host pointers.  `stream` is a hipStream_t (NULL is
+ * the default stream).  All calls only enqueue work on `stream` unless stated.
+ *
+ * Errors: every call returns an mppi_status; arguments are validated on the
+ * host before any device call.  MPPI_EINVAL: bad sizes, parameters or NULL
+ * pointers.  MPPI_EUNSUPPORTED: a valid request beyond this library's limits.
+ * MPPI_EDEVICE: no usable HIP device or a HIP runtime failure.  The message of
+ * the last failure on the calling thread is returned by mppi_last_error().
+ */
+#ifndef RAMPPI_H
+#define RAMPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mppi_handle mppi_handle;
+
+typedef enum {
+    MPPI_OK = 0,
+    MPPI_EINVAL = -1,
+    MPPI_ENOMEM = -2,
+    MPPI_EDEVICE = -3,
+    MPPI_EUNSUPPORTED = -4
+} mppi_status;
+
+enum {
+    MPPI_F_DEBUG = 1u,            /* also write L (K x M) and normalised weights */
+    MPPI_F_SHIFT = 2u,            /* V <- V+ shifted left by one step, last repeated */
+    MPPI_F_ALLOW_ZERO_NOISE = 4u  /* accept zero variances (then gamma must be 0) */
+};
+
+/* Library limits (MPPI_EUNSUPPORTED beyond them). */
+#define MPPI_MAX_M 1024
+#define MPPI_MAX_OBS 1024
+#define MPPI_MAX_T 4096
+
+/*
+ * Controller parameters.  Every field is read by mppi_create and copied.
+ *   K, T, M      samples, horizon, disturbance draws per sample (K, T, M >= 1).
+ *   n_obs        number of circular obstacles (>= 0).
+ *   dt           Euler step [s] (> 0); wheelbase [m] (> 0) of the bicycle.
+ *   u_lo, u_hi   control box, (acceleration, steering); u_lo < u_hi.
+ *   sigma_eps    control-noise variances (Eq. 2c), > 0.
+ *   sigma_w      state-disturbance variances for (x, y, psi, v), >= 0.
+ *   alpha        CVaR level in (0, 1) (Eq. 10-11).
+ *   lambda       temperature of the weights (Eq. 5, 17), > 0.
+ *   gamma        control-cost weight in [0, lambda] (Eq. 3).
+ *   eta          share of zero-mean samples in [0, 1] (Algorithm 1).
+ *   A, B, C_u    CVaR penalty gain, risk-scaling factor, CVaR bound (Eq. 14-19).
+ *   c_bdry, c_obs, c_dev, c_v, v_ref   running-cost weights (Eq. 20-22):
+ *                q = c_bdry mu_bdry + c_obs mu_obs + c_dev e^2 + c_v (v - v_ref)^2.
+ *   c4, c5       terminal cost phi = c4 - c5 s(x_T) (Eq. 23).
+ *   track        elliptic centreline: centre (ox, oy), semi-axes (a, b) > 0,
+ *                half width; e is the signed Sampson distance to it.
+ *   seed         Philox4x32-10 key (low word, high word).
+ *   flags        MPPI_F_* bits.
+ */
+typedef struct {
+    int32_t K, T, M, n_obs;
+    float dt, wheelbase;
+    float u_lo[2], u_hi[2];
+    float sigma_eps[2];
+    float sigma_w[4];
+    float alpha, lambda, gamma, eta, A, B, C_u;
+    float c_bdry, c_obs, c_dev, c_v, v_ref, c4, c5;
+    float track[5];
+    uint64_t seed;
+    uint32_t flags;
+} mppi_params;
+
+/* Device pointers into the workspace, valid while the handle lives.
+ *   u        T x K x 2 sampled controls, time-major: u[(t*K + k)*2 + c].
+ *   S        K nominal costs (Eq. 3).
+ *   L        K x M risk costs (Eq. 9), row-major; written with MPPI_F_DEBUG.
+ *   cvar     K CVaR values (Eq. 12, on the scaled costs of Eq. 18).
+ *   S_tilde  K modified costs (Eq. 16).
+ *   w_hat    K normalised weights (Eq. 17); written with MPPI_F_DEBUG.
+ *   u0       2 floats: the first command of V+ before any shift. */
+typedef struct {
+    const float *u, *S, *L, *cvar, *S_tilde, *w_hat, *u0;
+} mppi_debug_ptrs;
+
+/* Checks a parameter set without touching any device (Algorithm 1 inputs).
+ * Returns MPPI_OK, MPPI_EINVAL or MPPI_EUNSUPPORTED. */
+mppi_status mppi_validate(const mppi_params *p);
+
+/* Bytes of device workspace a handle with these parameters needs; 0 when
+ * mppi_validate rejects them.  No device call. */
+size_t mppi_workspace_bytes(const mppi_params *p);
+
+/* Creates a controller.  obstacles_host: n_obs x 3 floats (cx, cy, r), r > 0,
+ * copied into the workspace on `stream` (may be NULL when n_obs == 0).
+ * workspace_dev: caller-owned device memory of at least
+ * mppi_workspace_bytes(p) bytes, 256-byte aligned, which must outlive the
+ * handle.  On success *out receives the handle.  Synchronises `stream` once. */
+mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
+                        void *workspace_dev, size_t workspace_bytes,
+                        void *stream, mppi_handle **out);
+
+/* One RA-MPPI iteration (Algorithm 1, one pass of its loop).
+ *   x0        host, 4 floats: the measured state (finite).
+ *   V_dev     device, T x 2 floats row-major: in, the mean sequence V; out, V+
+ *             (Eq. 4), shifted when MPPI_F_SHIFT is set.
+ *   step_idx  call counter; it is the fourth Philox counter word, so the same
+ *             (seed, step_idx, x0, V) reproduces the same result bit for bit.
+ *   u0_host   NULL, or host memory for 2 floats: the first command of V+
+ *             before any shift.  When set, the call waits for the step.
+ * Enqueues three kernels on `stream` and returns. */
+mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
+                      uint32_t step_idx, float *u0_host, void *stream);
+
+/* Destroys the host handle (NULL is accepted); the workspace stays the
+ * caller's.  Waits for nothing: the caller must not free the workspace while
+ * a step is still running on the device. */
+mppi_status mppi_destroy(mppi_handle *h);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char *mppi_last_error(void);
+
+/* Device pointers of the intermediate results of the last step. */
+mppi_status mppi_debug_view(const mppi_handle *h, mppi_debug_ptrs *out);
+
+/* Kernel timing with HIP events recorded on the step's stream around the
+ * rollout kernel and around the two update kernels.  enable != 0 starts
+ * recording (and clears earlier records); mppi_timing_read waits for the
+ * recorded steps, returns the summed milliseconds and the step count, and
+ * clears the records.  At most 4096 steps are kept. */
+mppi_status mppi_timing_enable(mppi_handle *h, int enable);
+mppi_status mppi_timing_read(mppi_handle *h, double *rollout_ms, double *update_ms, int32_t *n_steps);
+
+/* ---- Stage entry points (same device code as the fused step) ---- */
+
+/* Philox4x32-10 (Salmon et al. 2011) of n counters: ctr_dev n x 4 uint32,
+ * out_dev n x 4 uint32, key = (seed low word, seed high word). */
+mppi_status mppi_philox(uint64_t seed, const uint32_t *ctr_dev, uint32_t *out_dev,
+                        int64_t n, void *stream);
+
+/* Box-Muller normals from the Philox words of n counters: out_dev n x 4 floats,
+ * (z0, z1) from words (0, 1) and (z2, z3) from words (2, 3); each word r maps
+ * to the uniform ((r >> 9) + 1/2) 2^-23. */
+mppi_status mppi_normals(uint64_t seed, const uint32_t *ctr_dev, float *out_dev,
+                         int64_t n, void *stream);
+
+/* Per-row CVaR (Eq. 10-13 on the scaled costs of Eq. 18-19): L_dev K x M
+ * floats row-major, cvar_dev K floats: the mean of the M - ceil(alpha M) + 1
+ * largest values of B (L - mean) + mean.  1 <= M <= MPPI_MAX_M. */
+mppi_status mppi_cvar(const float *L_dev, int32_t K, int32_t M, float alpha, float B,
+                      float *cvar_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAMPPI_H */

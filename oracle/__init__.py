@@ -106,14 +106,16 @@ def _load():
         lib.orc_update.argtypes = [P(D), P(D), ctypes.c_int, ctypes.c_int, P(D)]
         lib.orc_shift.argtypes = [P(D), ctypes.c_int, P(D)]
         lib.orc_controls.argtypes = [P(_Params), P(D), ctypes.c_uint32, P(D)]
-        lib.orc_nominal_cost.argtypes = [P(_Params), P(D), P(D), P(D), P(D), P(D)]
+        lib.orc_nominal_cost.argtypes = [P(_Params), P(D), P(D), P(D), P(D), P(D), P(D)]
         lib.orc_nominal_cost.restype = D
         lib.orc_disturbed_cost.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_uint32, P(D)]
+                                           ctypes.c_uint32, P(D), P(D)]
         lib.orc_disturbed_cost.restype = D
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_get_threads.restype = ctypes.c_int
-        lib.orc_step.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_uint32] + [P(D)] * 10
+        lib.orc_step.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_uint32] + [P(D)] * 12
+        lib.orc_track_radius.argtypes = [P(_Params), P(D)]
+        lib.orc_track_radius.restype = D
         lib.orc_step.restype = ctypes.c_int
         lib.orc_rollout_subset.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_uint32, ctypes.c_int,
                                            ctypes.c_int, P(D), P(D)]
@@ -248,6 +250,12 @@ def running_cost(p: dict, obs, x) -> float:
     return _load().orc_running_cost(ctypes.byref(s), _dptr(o), _dptr(xa))
 
 
+def track_radius(p: dict, x) -> float:
+    s = make_params(p, 0)
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    return _load().orc_track_radius(ctypes.byref(s), _dptr(xa))
+
+
 def progress(p: dict, x0, x) -> float:
     s = make_params(p, 0)
     a0 = np.ascontiguousarray(np.asarray(x0, dtype=np.float64))
@@ -329,26 +337,29 @@ def controls(p: dict, V, step_idx: int) -> np.ndarray:
     return out
 
 
-def nominal_cost(p: dict, obs, x0, V, uk) -> tuple[float, float]:
+def nominal_cost(p: dict, obs, x0, V, uk) -> tuple[float, float, float]:
+    """(S, obstacle margin, minimum normalised track radius) of one sample."""
     o = _as_f64(obs).reshape(-1, 3)
     s = make_params(p, o.shape[0])
     a0 = _as_f64(x0)
     Va = _as_f64(V).reshape(-1)
     ua = np.ascontiguousarray(np.asarray(uk, dtype=np.float64).reshape(-1))
-    mg = ctypes.c_double()
-    S = _load().orc_nominal_cost(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(Va), _dptr(ua), ctypes.byref(mg))
-    return S, mg.value
+    mg, cd = ctypes.c_double(), ctypes.c_double()
+    S = _load().orc_nominal_cost(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(Va), _dptr(ua), ctypes.byref(mg),
+                                 ctypes.byref(cd))
+    return S, mg.value, cd.value
 
 
-def disturbed_cost(p: dict, obs, x0, uk, k: int, m: int, step_idx: int) -> tuple[float, float]:
+def disturbed_cost(p: dict, obs, x0, uk, k: int, m: int, step_idx: int) -> tuple[float, float, float]:
+    """(L, obstacle margin, minimum normalised track radius) of one draw."""
     o = _as_f64(obs).reshape(-1, 3)
     s = make_params(p, o.shape[0])
     a0 = _as_f64(x0)
     ua = np.ascontiguousarray(np.asarray(uk, dtype=np.float64).reshape(-1))
-    mg = ctypes.c_double()
+    mg, cd = ctypes.c_double(), ctypes.c_double()
     L = _load().orc_disturbed_cost(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(ua), int(k), int(m),
-                                   int(step_idx) & 0xFFFFFFFF, ctypes.byref(mg))
-    return L, mg.value
+                                   int(step_idx) & 0xFFFFFFFF, ctypes.byref(mg), ctypes.byref(cd))
+    return L, mg.value, cd.value
 
 
 def set_threads(n: int) -> None:
@@ -370,11 +381,13 @@ def step(p: dict, obs, x0, V, step_idx: int) -> dict:
         "u": np.zeros((K, T, 2)), "S": np.zeros(K), "L": np.zeros((K, M)), "cvar": np.zeros(K),
         "S_tilde": np.zeros(K), "w_hat": np.zeros(K), "V_plus": np.zeros((T, 2)),
         "V_next": np.zeros((T, 2)), "obs_margin": np.zeros((K, M)), "nom_margin": np.zeros(K),
+        "obs_cond": np.zeros((K, M)), "nom_cond": np.zeros(K),
     }
     rc = _load().orc_step(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(Va), int(step_idx) & 0xFFFFFFFF,
                           _dptr(out["u"]), _dptr(out["S"]), _dptr(out["L"]), _dptr(out["cvar"]),
                           _dptr(out["S_tilde"]), _dptr(out["w_hat"]), _dptr(out["V_plus"]),
-                          _dptr(out["V_next"]), _dptr(out["obs_margin"]), _dptr(out["nom_margin"]))
+                          _dptr(out["V_next"]), _dptr(out["obs_margin"]), _dptr(out["nom_margin"]),
+                          _dptr(out["obs_cond"]), _dptr(out["nom_cond"]))
     if rc != 0:
         raise ValueError("oracle step rejected its arguments")
     out["u0"] = out["V_plus"][0].copy()

@@ -251,6 +251,17 @@ double orc_progress_margin(const orc_params *p, const double x0[4], const double
     return pi - fabs(orc_wrap(th - th0));
 }
 
+/* Normalised radius sqrt((X/a)^2 + (Y/b)^2) of the point (1 on the
+ * centreline, 0 at the ellipse centre).  Diagnostic: near the centre the
+ * gradient of G vanishes and the Sampson distance e = G / |grad G| becomes
+ * ill-conditioned (relative sensitivity about 1 / distance from the centre),
+ * so rollouts that pass there amplify rounding of the state. */
+double orc_track_radius(const orc_params *p, const double x[4])
+{
+    double X = (x[0] - p->track[0]) / p->track[2], Y = (x[1] - p->track[1]) / p->track[3];
+    return sqrt(X * X + Y * Y);
+}
+
 /* Terminal cost, Eq. 23: phi = c4 - c5 * s(x). */
 double orc_terminal_cost(const orc_params *p, const double x0[4], const double x[4])
 {
@@ -416,23 +427,29 @@ void orc_controls(const orc_params *p, const double *V, uint32_t step_idx, doubl
  * gamma * v_t^T Sigma_eps^-1 u_t (per step, on the applied control), plus the
  * terminal cost at x_T.  gamma == 0 drops the control term. */
 double orc_nominal_cost(const orc_params *p, const double *obs, const double x0[4],
-                        const double *V, const double *uk, double *margin)
+                        const double *V, const double *uk, double *margin, double *cond)
 {
     double x[4] = { x0[0], x0[1], x0[2], x0[3] }, xn[4];
-    double S = 0.0, mg = INFINITY;
+    double S = 0.0, mg = INFINITY, cd = INFINITY;
     for (int t = 0; t < p->T; ++t) {
         const double *ut = uk + 2 * t;
         S += orc_running_cost(p, obs, x);
         if (p->gamma != 0.0)
             S += p->gamma * (V[2 * t] * ut[0] / p->sigma_eps[0] + V[2 * t + 1] * ut[1] / p->sigma_eps[1]);
-        double g = orc_obstacle_margin(obs, p->n_obs, x[0], x[1]);
-        if (g < mg) mg = g;
+        if (margin) {
+            double g = orc_obstacle_margin(obs, p->n_obs, x[0], x[1]);
+            if (g < mg) mg = g;
+        }
+        if (cond) {
+            double r = orc_track_radius(p, x);
+            if (r < cd) cd = r;
+        }
         orc_dynamics(x, ut, p->dt, p->wheelbase, xn);
         memcpy(x, xn, sizeof x);
     }
     if (p->c4 != 0.0 || p->c5 != 0.0) {
         S += orc_terminal_cost(p, x0, x);
-        if (p->c5 != 0.0) {
+        if (margin && p->c5 != 0.0) {
             /* the wrap in s(x) is a discontinuity of phi; express its margin in
              * metres of progress so it can share the obstacle-margin threshold */
             double g = orc_progress_margin(p, x0, x) * 0.5 * (p->track[2] + p->track[3]);
@@ -440,6 +457,7 @@ double orc_nominal_cost(const orc_params *p, const double *obs, const double x0[
         }
     }
     if (margin) *margin = mg;
+    if (cond) *cond = cd;
     return S;
 }
 
@@ -447,16 +465,22 @@ double orc_nominal_cost(const orc_params *p, const double *obs, const double x0[
  * x~_{t+1} = F(x~_t, u_t) + w_t with w_t = sqrt(diag Sigma_w) * z (additive
  * zero-mean noise, so that F = E[F~] as Eq. 7 requires); l = q. */
 double orc_disturbed_cost(const orc_params *p, const double *obs, const double x0[4],
-                          const double *uk, int k, int m, uint32_t step_idx, double *margin)
+                          const double *uk, int k, int m, uint32_t step_idx, double *margin, double *cond)
 {
     double sw[4];
     for (int i = 0; i < 4; ++i) sw[i] = sqrt(p->sigma_w[i]);
     double x[4] = { x0[0], x0[1], x0[2], x0[3] }, xn[4];
-    double L = 0.0, mg = INFINITY;
+    double L = 0.0, mg = INFINITY, cd = INFINITY;
     for (int t = 0; t < p->T; ++t) {
         L += orc_running_cost(p, obs, x);
-        double g = orc_obstacle_margin(obs, p->n_obs, x[0], x[1]);
-        if (g < mg) mg = g;
+        if (margin) {
+            double g = orc_obstacle_margin(obs, p->n_obs, x[0], x[1]);
+            if (g < mg) mg = g;
+        }
+        if (cond) {
+            double r = orc_track_radius(p, x);
+            if (r < cd) cd = r;
+        }
         uint32_t ctr[4] = { (uint32_t)t, (uint32_t)m, (uint32_t)k, step_idx };
         double z[4];
         orc_normals4(ctr, p->seed, z);
@@ -464,6 +488,7 @@ double orc_disturbed_cost(const orc_params *p, const double *obs, const double x
         for (int i = 0; i < 4; ++i) x[i] = xn[i] + sw[i] * z[i];
     }
     if (margin) *margin = mg;
+    if (cond) *cond = cd;
     return L;
 }
 
@@ -471,7 +496,8 @@ double orc_disturbed_cost(const orc_params *p, const double *obs, const double x
 /* One full RA-MPPI iteration (Algorithm 1, one pass of the while loop).     */
 /* Outputs (all caller-allocated, any may be NULL except Vplus):              */
 /*   u [K*T*2], S [K], L [K*M], cvar [K], St [K], w_hat [K], Vplus [T*2],      */
-/*   Vnext [T*2] (shifted when p->shift), obs_margin [K*M], nom_margin [K].    */
+/*   Vnext [T*2] (shifted when p->shift), obs_margin [K*M], nom_margin [K],    */
+/*   obs_cond [K*M], nom_cond [K] (minimum normalised track radius).           */
 /* Returns 0, or -1 on invalid sizes.                                         */
 /* ------------------------------------------------------------------------ */
 static int g_threads = 1;
@@ -483,7 +509,7 @@ int orc_get_threads(void) { return g_threads; }
 int orc_step(const orc_params *p, const double *obs, const double x0[4], const double *V,
              uint32_t step_idx, double *u_out, double *S_out, double *L_out, double *cvar_out,
              double *St_out, double *w_hat_out, double *Vplus, double *Vnext,
-             double *obs_margin, double *nom_margin)
+             double *obs_margin, double *nom_margin, double *obs_cond, double *nom_cond)
 {
     int K = p->K, T = p->T, M = p->M;
     if (K <= 0 || T <= 0 || M <= 0 || p->n_obs < 0 || !Vplus) return -1;
@@ -509,13 +535,16 @@ int orc_step(const orc_params *p, const double *obs, const double x0[4], const d
 #endif
     for (int k = 0; k < K; ++k) {
         const double *uk = u + (size_t)k * T * 2;
-        double nm;
-        S[k] = orc_nominal_cost(p, obs, x0, V, uk, &nm);
+        double nm, nc;
+        S[k] = orc_nominal_cost(p, obs, x0, V, uk, nom_margin ? &nm : NULL, nom_cond ? &nc : NULL);
         if (nom_margin) nom_margin[k] = nm;
+        if (nom_cond) nom_cond[k] = nc;
         for (int m = 0; m < M; ++m) {
-            double om;
-            L[(size_t)k * M + m] = orc_disturbed_cost(p, obs, x0, uk, k, m, step_idx, &om);
+            double om, oc;
+            L[(size_t)k * M + m] = orc_disturbed_cost(p, obs, x0, uk, k, m, step_idx, obs_margin ? &om : NULL,
+                                                      obs_cond ? &oc : NULL);
             if (obs_margin) obs_margin[(size_t)k * M + m] = om;
+            if (obs_cond) obs_cond[(size_t)k * M + m] = oc;
         }
         double *work = (double *)malloc(sizeof(double) * (size_t)M);
         cv[k] = orc_cvar_with(L + (size_t)k * M, M, p->alpha, p->B, work);
@@ -555,9 +584,9 @@ int orc_rollout_subset(const orc_params *p, const double *obs, const double x0[4
         int k = k0 + j;
         double *uk = (double *)malloc(sizeof(double) * (size_t)T * 2);
         for (int t = 0; t < T; ++t) orc_sample_control(p, V, step_idx, n_warm, k, t, uk + 2 * t);
-        S_out[j] = orc_nominal_cost(p, obs, x0, V, uk, NULL);
+        S_out[j] = orc_nominal_cost(p, obs, x0, V, uk, NULL, NULL);
         for (int m = 0; m < M; ++m)
-            L_out[(size_t)j * M + m] = orc_disturbed_cost(p, obs, x0, uk, k, m, step_idx, NULL);
+            L_out[(size_t)j * M + m] = orc_disturbed_cost(p, obs, x0, uk, k, m, step_idx, NULL, NULL);
         free(uk);
     }
     return 0;

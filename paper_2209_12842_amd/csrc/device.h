@@ -1,0 +1,220 @@
+// Device building blocks of the RA-MPPI step for gfx950 (MI355X).
+//
+// Noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the Box-Muller
+// transform (Box & Muller 1958).  Model: rear-axle kinematic bicycle with a
+// forward-Euler step (Eq. 1).  Costs: the running cost of Eq. 20-22 on an
+// elliptic centreline with the signed Sampson distance, the terminal cost of
+// Eq. 23.  Risk: the tail mean of Eq. 10-13 on the scaled costs of Eq. 18-19.
+//
+// All arithmetic is FP32 (round to nearest even, no fast-math), except the
+// integer Philox rounds and the integer collision counts.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ramppi {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
+// Second counter word of the control-noise stream (disturbance draws use m).
+constexpr uint32_t kCtrlWord = 0xFFFFFFFFu;
+
+// Philox4x32 with 10 rounds.  Round: words 0 and 2 are multiplied by the two
+// multipliers (full 64-bit products); the new counter is
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key
+// then advances by the two Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = c0 * kPhiloxM0;
+        const uint32_t hi0 = __umulhi(c0, kPhiloxM0);
+        const uint32_t lo1 = c2 * kPhiloxM1;
+        const uint32_t hi1 = __umulhi(c2, kPhiloxM1);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// uint32 -> (0, 1): ((r >> 9) + 1/2) 2^-23, exact in FP32.
+__device__ __forceinline__ float uniform01(uint32_t r) {
+    return __fmaf_rn((float)(r >> 9), 0x1p-23f, 0x1p-24f);
+}
+
+// Two standard normals from two uniforms (Box-Muller).
+__device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
+    const float rad = sqrtf(-2.0f * logf(u0));
+    float s, c;
+    sincospif(2.0f * u1, &s, &c);
+    z0 = rad * c;
+    z1 = rad * s;
+}
+
+__device__ __forceinline__ float4 normals4(uint4 r) {
+    float4 z;
+    box_muller(uniform01(r.x), uniform01(r.y), z.x, z.y);
+    box_muller(uniform01(r.z), uniform01(r.w), z.z, z.w);
+    return z;
+}
+
+// Per-launch constants of one step, passed by value as a kernel argument.
+struct StepConst {
+    int32_t K, T, M, n_obs;
+    int32_t spb;         // samples per disturbed workgroup
+    int32_t n_nom_wg;    // nominal workgroups at the front of the grid
+    int32_t n_warm;      // samples k < n_warm keep the mean sequence
+    int32_t n_tail;      // M - ceil(alpha M) + 1
+    float dt, inv_wheelbase;
+    float u_lo0, u_lo1, u_hi0, u_hi1;
+    float se0, se1;      // control-noise standard deviations
+    float sw0, sw1, sw2, sw3;  // disturbance standard deviations
+    float gamma, inv_var0, inv_var1;
+    float A, B, C_u, lambda;
+    float c_bdry, c_obs, c_dev, c_v, v_ref, c4, c5;
+    // track: offsets of the local frame from the ellipse centre, and shape
+    float tox, toy, inv_a, inv_b, g_a, g_b, hw, half_ab;
+    float theta0;        // ellipse angle of the start point
+    float psi0, v0;      // start heading and speed (position is the frame origin)
+    float fx, fy;        // frame origin (the start position)
+    uint32_t key0, key1, step_idx, flags;
+    int32_t use_bdry, use_term, use_ctrl, scale_risk, debug;
+};
+
+struct State {
+    float x, y, psi, v;  // position in the local frame
+};
+
+// Forward-Euler bicycle step: da = dt a, kappa = tan(delta) / wheelbase.
+__device__ __forceinline__ void bicycle_step(State& s, float da, float kappa, float dt) {
+    float sn, cs;
+    sincosf(s.psi, &sn, &cs);
+    const float dv = dt * s.v;
+    s.x = __fmaf_rn(dv, cs, s.x);
+    s.y = __fmaf_rn(dv, sn, s.y);
+    s.psi = __fmaf_rn(dv, kappa, s.psi);
+    s.v = s.v + da;
+}
+
+// Track and speed terms of q: c_dev e^2 + c_v (v - v_ref)^2 [+ c_bdry mu_bdry].
+__device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s) {
+    const float X = s.x + c.tox;
+    const float Y = s.y + c.toy;
+    const float xa = X * c.inv_a;
+    const float yb = Y * c.inv_b;
+    const float G = __fmaf_rn(xa, xa, __fmaf_rn(yb, yb, -1.0f));
+    const float gx = X * c.g_a;   // 2 X / a^2
+    const float gy = Y * c.g_b;   // 2 Y / b^2
+    const float gn2 = fmaxf(__fmaf_rn(gx, gx, gy * gy), 1e-24f);
+    const float dv = s.v - c.v_ref;
+    float q = __fmaf_rn(c.c_v * dv, dv, c.c_dev * (G * G / gn2));
+    if (c.use_bdry) {
+        const float e = G * rsqrtf(gn2);
+        const float d = c.hw - fabsf(e);
+        const float mu = fmaxf(0.0f, atanf(-100.0f * d) * 0.318309886183790671538f + 0.5f);
+        q = __fmaf_rn(c.c_bdry, mu, q);
+    }
+    return q;
+}
+
+// Number of obstacle discs strictly containing the point (Eq. 22 summed over
+// obstacles).  tab[i] = (-2 cx, -2 cy, cx^2 + cy^2 - r^2) in the local frame,
+// so that |p - c|^2 - r^2 = |p|^2 + tab.x px + tab.y py + tab.z.
+__device__ __forceinline__ int obstacle_hits(const float4* __restrict__ tab, int n_obs, float px, float py) {
+    const float neg_rho = -__fmaf_rn(px, px, py * py);
+    int cnt = 0;
+    int i = 0;
+    for (; i + 4 <= n_obs; i += 4) {
+        const float4 o0 = tab[i], o1 = tab[i + 1], o2 = tab[i + 2], o3 = tab[i + 3];
+        cnt += (__fmaf_rn(o0.x, px, __fmaf_rn(o0.y, py, o0.z)) < neg_rho);
+        cnt += (__fmaf_rn(o1.x, px, __fmaf_rn(o1.y, py, o1.z)) < neg_rho);
+        cnt += (__fmaf_rn(o2.x, px, __fmaf_rn(o2.y, py, o2.z)) < neg_rho);
+        cnt += (__fmaf_rn(o3.x, px, __fmaf_rn(o3.y, py, o3.z)) < neg_rho);
+    }
+    for (; i < n_obs; ++i) {
+        const float4 o = tab[i];
+        cnt += (__fmaf_rn(o.x, px, __fmaf_rn(o.y, py, o.z)) < neg_rho);
+    }
+    return cnt;
+}
+
+// Sampled control (Eq. 2b-2c with the warm / zero-mean rule of Algorithm 1):
+// u = clamp(base + sqrt(Sigma_eps) z, u_lo, u_hi), base = v_t for k < n_warm.
+__device__ __forceinline__ float2 sample_control(const StepConst& c, const float* __restrict__ V, int k, int t) {
+    const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1);
+    float z0, z1;
+    box_muller(uniform01(r.x), uniform01(r.y), z0, z1);
+    float b0 = 0.0f, b1 = 0.0f;
+    if (k < c.n_warm) {
+        b0 = V[2 * t];
+        b1 = V[2 * t + 1];
+    }
+    float a = __fmaf_rn(c.se0, z0, b0);
+    float d = __fmaf_rn(c.se1, z1, b1);
+    a = fminf(fmaxf(a, c.u_lo0), c.u_hi0);
+    d = fminf(fmaxf(d, c.u_lo1), c.u_hi1);
+    return make_float2(a, d);
+}
+
+// Angle wrap to (-pi, pi].
+__device__ __forceinline__ float wrap_pi(float ang) {
+    const float two_pi = 6.28318530717958647692f;
+    const float pi = 3.14159265358979323846f;
+    return ang - two_pi * ceilf((ang - pi) * (1.0f / two_pi));
+}
+
+// Terminal cost, Eq. 23, with s(x) the mean-radius arc of the ellipse angle.
+__device__ __forceinline__ float terminal_cost(const StepConst& c, const State& s) {
+    const float X = s.x + c.tox;
+    const float Y = s.y + c.toy;
+    const float th = atan2f(Y * c.inv_b, X * c.inv_a);
+    const float prog = c.half_ab * wrap_pi(th - c.theta0);
+    return c.c4 - c.c5 * prog;
+}
+
+// Tail mean over the M (scaled) risk costs of one sample, held in LDS
+// (vals[0..M-1]); each of the M lanes calls it with its own index m.  The
+// lane's rank counts the strictly larger values plus the equal values with a
+// smaller index, so ranks are a permutation of 0..M-1 and the n_tail largest
+// values land, in descending order, in tail[0..n_tail-1].  The caller
+// synchronises the workgroup between this and tail_sum.
+__device__ __forceinline__ void tail_rank_scatter(const float* vals, float* tail, int M, int m, int n_tail) {
+    const float v = vals[m];
+    int rank = 0;
+    for (int j = 0; j < M; ++j) {
+        const float o = vals[j];
+        rank += (o > v) | ((o == v) & (j < m));
+    }
+    if (rank < n_tail) tail[rank] = v;
+}
+
+__device__ __forceinline__ float tail_sum(const float* tail, int n_tail) {
+    float s = 0.0f;
+    for (int r = 0; r < n_tail; ++r) s += tail[r];
+    return s / (float)n_tail;
+}
+
+// Wave64 reductions with a fixed butterfly order (results are identical on
+// every run and in every lane).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+}  // namespace ramppi

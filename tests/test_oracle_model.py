@@ -179,3 +179,11 @@ def test_terminal_cost_is_arc_length_on_a_circle():
     th = math.pi + 0.1
     x = [R * math.cos(th), R * math.sin(th), 0.0, 0.0]
     assert oracle.progress(p, x0, x) == pytest.approx(R * (th - 2 * math.pi), rel=1e-12)
+
+
+def test_track_radius_diagnostic():
+    p = dict(W.PRESETS["c2"])
+    assert oracle.track_radius(p, [50.0, 0.0, 0, 0]) == pytest.approx(1.0)
+    assert oracle.track_radius(p, [0.0, -20.0, 0, 0]) == pytest.approx(1.0)
+    assert oracle.track_radius(p, [0.0, 0.0, 0, 0]) == 0.0
+    assert oracle.track_radius(p, [25.0, 0.0, 0, 0]) == pytest.approx(0.5)

@@ -1,0 +1,259 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on MI355X.
+
+Noise: Philox words bit-exact; Box-Muller normals to FP32 rounding.  Stages:
+the CVaR kernel against the oracle's estimator on the same inputs, and
+against the Gaussian closed form.  Full step: the flip-aware protocol of
+parity_helpers on the small, paper-preset and receding-horizon workloads at
+their full sizes, on the largest workload through sampled rollouts and
+stage-wise checks, plus invariants, determinism and edge shapes.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2209_12842_amd import workloads as W
+
+from parity_helpers import check_step, gpu_step, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU hosts
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2209_12842_amd as R  # noqa: E402
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _threads():
+    oracle.set_threads(min(16, max(1, len(__import__("os").sched_getaffinity(0)))))
+    yield
+
+
+# ------------------------------------------------------------- noise ----
+
+def test_philox_bit_exact():
+    rng = np.random.default_rng(0)
+    n = 1 << 20
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:64] = np.array([[0, 0, 0, 0], [0xFFFFFFFF] * 4, [0, 0xFFFFFFFF, 0, 0xFFFFFFFF],
+                         [0xFFFFFFFF, 0, 0xFFFFFFFF, 0]] * 16, dtype=np.uint32)
+    for seed in (0, 0x5EED0003, 0xFFFFFFFFFFFFFFFF, 0x0123456789ABCDEF):
+        _log("philox seed %x" % seed)
+        g = R.philox(seed, torch.from_numpy(ctr.view(np.int32)).cuda()).cpu().numpy().view(np.uint32)
+        o = oracle.philox_batch(ctr, seed)
+        assert np.array_equal(g, o)
+
+
+def test_normals_match_oracle():
+    rng = np.random.default_rng(1)
+    n = 1 << 18
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    g = R.normals(0x5EED0002, torch.from_numpy(ctr.view(np.int32)).cuda()).cpu().numpy().astype(np.float64)
+    o = oracle.normals_batch(ctr, 0x5EED0002)
+    err = np.abs(g - o)
+    assert err.max() <= 4e-6 * max(1.0, np.abs(o).max()), err.max()
+    assert np.median(err) <= 1e-7
+
+
+# -------------------------------------------------------------- CVaR ----
+
+@pytest.mark.parametrize("K,M,alpha,B", [(1000, 16, 0.9, 1.0), (333, 64, 0.9, 1.0), (77, 128, 0.9, 1.0),
+                                         (50, 300, 0.9, 1.0), (9, 1024, 0.5, 1.0), (500, 7, 0.7, 1.0),
+                                         (300, 1, 0.9, 1.0), (257, 100, 0.95, 2.0), (64, 16, 0.05, 0.5)])
+def test_cvar_stage(K, M, alpha, B):
+    rng = np.random.default_rng(K * 1000 + M)
+    L = (rng.gamma(2.0, 5.0, size=(K, M)) + rng.integers(0, 3, size=(K, M)) * 1e4).astype(np.float32)
+    g = R.cvar(torch.from_numpy(L).cuda(), alpha, B).cpu().numpy().astype(np.float64)
+    o = oracle.cvar_batch(L.astype(np.float64), float(np.float32(alpha)), float(np.float32(B)))
+    assert np.all(rel_err(g, o) <= 1e-5), rel_err(g, o).max()
+
+
+def test_cvar_ties():
+    L = np.tile(np.array([1.0, 2.0, 2.0, 2.0, 5.0, 2.0, 2.0, 0.0], dtype=np.float32), (40, 1))
+    g = R.cvar(torch.from_numpy(L).cuda(), 0.7).cpu().numpy()
+    o = oracle.cvar_batch(L.astype(np.float64), float(np.float32(0.7)))
+    assert np.array_equal(g.astype(np.float64), o)
+
+
+def test_cvar_gaussian_closed_form():
+    from scipy import stats
+    mu, sigma, alpha = 4.0, 2.5, 0.9
+    rng = np.random.default_rng(7)
+    K, M = 4000, 1000
+    L = rng.normal(mu, sigma, size=(K, M)).astype(np.float32)
+    g = R.cvar(torch.from_numpy(L).cuda(), alpha).cpu().numpy().astype(np.float64)
+    o = oracle.cvar_batch(L.astype(np.float64), float(np.float32(alpha)))
+    assert np.all(rel_err(g, o) <= 1e-5)
+    # the per-row estimator at M = 1000 averages the 101 largest of 1000 draws;
+    # its mean is within a small bias of the closed form
+    ref = mu + sigma * stats.norm.pdf(stats.norm.ppf(alpha)) / (1 - alpha)
+    se = g.std(ddof=1) / np.sqrt(K)
+    assert abs(g.mean() - ref) < 3 * se + 0.01 * sigma, (g.mean(), ref, se)
+
+
+# --------------------------------------------------------- full step ----
+
+def _world(name, **kw):
+    w = W.make_world(name, **kw)
+    return w["params"], w["obstacles"], w["x0"], w["V0"]
+
+
+def _run(p, obs, x0, V0, step_idx, shift=False, strict=True, allow_zero=False):
+    _log("step %s K=%d T=%d M=%d n_obs=%d idx=%d" % (p.get("config_id"), p["K"], p["T"], p["M"], len(obs),
+                                                   step_idx))
+    ctl = R.Controller(p, obs, debug=True, allow_zero_noise=allow_zero)
+    g = gpu_step(ctl, x0, V0, step_idx)
+    o = oracle.step(p, obs, x0, V0, step_idx)
+    rep = check_step(p, g, o, shift=shift, strict_e2e=strict)
+    _log("  " + ", ".join("%s=%s" % kv for kv in rep.items()))
+    ctl.close()
+    return g, o, rep
+
+
+def test_step_c1():
+    p, obs, x0, V0 = _world("c1")
+    _, _, rep = _run(p, obs, x0, V0, 0)
+    assert rep["e2e_applies"]
+    _run(p, obs, x0, W.random_V(p["T"], 5, scale=(2.0, 0.4)), 3)
+
+
+def test_step_c2():
+    p, obs, x0, V0 = _world("c2")
+    _run(p, obs, x0, V0, 0, shift=True)
+
+
+def test_step_paper_preset_m128_and_m300():
+    p, obs, x0, V0 = _world("p0", M=128)
+    _run(p, obs, x0, W.random_V(p["T"], 6, scale=(1.0, 0.3)), 2)
+    p, obs, x0, V0 = _world("p0")
+    _run(p, obs, x0, V0, 1)
+
+
+def test_step_c3_sampled():
+    p, obs, x0, V0 = _world("c3")
+    _log("c3 full size, sampled")
+    ctl = R.Controller(p, obs, debug=True)
+    g = gpu_step(ctl, x0, V0, 0)
+    K, M = p["K"], p["M"]
+    alpha = float(np.float32(p["alpha"]))
+    lam = float(np.float32(p["lam"]))
+    # stage-wise on every sample
+    cv = oracle.cvar_batch(g["L"], alpha)
+    assert np.all(np.abs(g["cvar"] - cv) <= 20 * 4 * 2.0 ** -24 * np.maximum(np.abs(g["L"]).max(axis=1), 1))
+    _, wh = oracle.weights(g["S_tilde"], lam)
+    assert np.abs(g["w_hat"] - wh).max() <= 1e-5
+    assert np.abs(g["V_next"] - oracle.update(wh, g["u"])).max() <= 1e-5
+    # the oracle's own rollouts of a spread of samples, including the best
+    ks = sorted(set(list(np.linspace(0, K - 1, 12).astype(int)) + [int(np.argmin(g["S_tilde"]))]))
+    u_o = oracle.controls(dict(p, K=K), V0, 0)
+    assert np.abs(u_o - g["u"]).max() <= 1e-5
+    n_bad = 0
+    for k in ks:
+        S, L = oracle.rollout_subset(p, obs, x0, V0, 0, k, 1)
+        Sn, mg, cd = oracle.nominal_cost(p, obs, x0, V0, u_o[k])
+        assert Sn == S[0]
+        eS = rel_err(g["S"][k], S[0])
+        if mg >= 1e-3 and cd >= 0.25:
+            assert eS <= 1e-4, (k, eS)
+        diag = np.array([oracle.disturbed_cost(p, obs, x0, u_o[k], k, m, 0)[1:] for m in range(M)])
+        eL = rel_err(g["L"][k], L[0])
+        ok = (diag[:, 0] >= 1e-3) & (diag[:, 1] >= 0.25)
+        n_bad += int((~ok).sum())
+        assert np.all(eL[ok] <= 1e-4), (k, eL.max())
+    assert n_bad <= 0.01 * len(ks) * M
+    ctl.close()
+
+
+def test_closed_loop_c2_steps():
+    # receding horizon with shift: each device step is checked against the
+    # oracle run from the same state and the same incoming mean sequence
+    p, obs, x0, V0 = _world("c2", K=512)
+    ctl = R.Controller(p, obs, debug=True)
+    V = ctl.new_V(V0)
+    x = np.asarray(x0, dtype=np.float64)
+    for j in range(4):
+        Vin = V.detach().cpu().numpy().copy()
+        u0 = ctl.step(x.astype(np.float32), V, j)
+        torch.cuda.synchronize()
+        d = ctl.debug()
+        g = {k: v.detach().cpu().numpy().astype(np.float64) for k, v in d.items()}
+        g["u"] = np.transpose(g["u"], (1, 0, 2))
+        g["V_next"] = V.detach().cpu().numpy().astype(np.float64)
+        g["u0_host"] = u0.astype(np.float64)
+        o = oracle.step(p, obs, x.astype(np.float32), Vin, j)
+        rep = check_step(p, g, o, shift=True)
+        _log("  loop %d: %s" % (j, rep))
+        # host plant: the nominal model plus a Philox disturbance
+        z = oracle.normals4(W.plant_noise_counter(j), p["seed"])
+        x = oracle.dynamics(x, u0.astype(np.float64), float(np.float32(p["dt"])),
+                            float(np.float32(p["wheelbase"])))
+        x = x + np.sqrt(np.float32(p["sigma_w"]).astype(np.float64)) * z
+    ctl.close()
+
+
+def test_determinism():
+    p, obs, x0, V0 = _world("c1")
+    ctl = R.Controller(p, obs, debug=True)
+    a = gpu_step(ctl, x0, V0, 4)
+    b = gpu_step(ctl, x0, V0, 4)
+    for k in ("S", "L", "cvar", "S_tilde", "w_hat", "V_next", "u"):
+        assert np.array_equal(a[k], b[k]), k
+    c = gpu_step(ctl, x0, V0, 5)
+    assert not np.array_equal(a["L"], c["L"])
+    ctl.close()
+
+
+def test_zero_disturbance_matches_nominal_on_device():
+    p, obs, x0, V0 = _world("c1", sigma_w=(0.0, 0.0, 0.0, 0.0), gamma=0.0)
+    ctl = R.Controller(p, obs, debug=True)
+    g = gpu_step(ctl, x0, V0, 0)
+    assert np.all(rel_err(g["L"], g["S"][:, None]) <= 1e-6)
+    frac_exact = float((g["L"] == g["S"][:, None]).mean())
+    _log("bitwise-equal fraction %.4f" % frac_exact)
+    assert np.all(rel_err(g["cvar"], g["S"]) <= 1e-6)
+    ctl.close()
+
+
+def test_zero_control_noise_returns_clamped_mean_on_device():
+    p, obs, x0, _ = _world("c1", sigma_eps=(0.0, 0.0), gamma=0.0)
+    V0 = W.random_V(p["T"], 9, scale=(4.0, 0.8))
+    ctl = R.Controller(p, obs, debug=True, allow_zero_noise=True)
+    g = gpu_step(ctl, x0, V0, 0)
+    Vc = np.clip(V0.astype(np.float64), p["u_lo"], p["u_hi"])
+    assert np.abs(g["V_next"] - Vc).max() <= 1e-6
+    ctl.close()
+
+
+def test_plain_mppi_ignores_disturbances_on_device():
+    p, obs, x0, V0 = _world("c1", A=0.0)
+    a = gpu_step(R.Controller(p, obs, debug=True), x0, V0, 2)
+    b = gpu_step(R.Controller(dict(p, M=32, sigma_w=(0.5, 0.5, 0.1, 1.0)), obs, debug=True), x0, V0, 2)
+    assert np.array_equal(a["V_next"], b["V_next"])
+    assert np.array_equal(a["S_tilde"], a["S"])
+
+
+@pytest.mark.parametrize("kw", [dict(K=1, M=1, T=1), dict(K=257, M=16, T=7), dict(K=33, M=7, T=5),
+                                dict(K=20, M=300, T=6), dict(K=5, M=1024, T=4), dict(K=300, M=64, T=3, n_obs=0),
+                                dict(K=64, M=16, T=9, eta=0.5, B=3.0, C_u=60.0, lam=20.0)])
+def test_edge_shapes(kw):
+    kw = dict(kw)
+    n_obs = kw.pop("n_obs", None)
+    p, obs, x0, _ = _world("c1", **kw)
+    if n_obs is not None:
+        obs = obs[:n_obs]
+    V0 = W.random_V(p["T"], 3, scale=(1.0, 0.2))
+    _run(p, obs, x0, V0, 1)
+
+
+def test_shift_and_first_command():
+    p, obs, x0, V0 = _world("c1", shift=True)
+    g, o, rep = _run(p, obs, x0, V0, 0, shift=True)
+    assert np.abs(g["u0_host"] - o["u0"]).max() <= 1e-3
