@@ -128,7 +128,7 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
  *             (seed, step_idx, x0, V) reproduces the same result bit for bit.
  *   u0_host   NULL, or host memory for 2 floats: the first command of V+
  *             before any shift.  When set, the call waits for the step.
- * Enqueues three kernels on `stream` and returns. */
+ * Enqueues four kernels on `stream` and returns. */
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
 

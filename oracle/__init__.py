@@ -370,8 +370,9 @@ def get_threads() -> int:
     return _load().orc_get_threads()
 
 
-def step(p: dict, obs, x0, V, step_idx: int) -> dict:
-    """One RA-MPPI iteration (Algorithm 1).  Returns every intermediate."""
+def step(p: dict, obs, x0, V, step_idx: int, diagnostics: bool = True) -> dict:
+    """One RA-MPPI iteration (Algorithm 1).  Returns every intermediate; the
+    margin and conditioning diagnostics are computed only when asked for."""
     o = _as_f64(obs).reshape(-1, 3)
     s = make_params(p, o.shape[0])
     K, T, M = s.K, s.T, s.M
@@ -386,8 +387,9 @@ def step(p: dict, obs, x0, V, step_idx: int) -> dict:
     rc = _load().orc_step(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(Va), int(step_idx) & 0xFFFFFFFF,
                           _dptr(out["u"]), _dptr(out["S"]), _dptr(out["L"]), _dptr(out["cvar"]),
                           _dptr(out["S_tilde"]), _dptr(out["w_hat"]), _dptr(out["V_plus"]),
-                          _dptr(out["V_next"]), _dptr(out["obs_margin"]), _dptr(out["nom_margin"]),
-                          _dptr(out["obs_cond"]), _dptr(out["nom_cond"]))
+                          _dptr(out["V_next"]), *(
+                              (_dptr(out["obs_margin"]), _dptr(out["nom_margin"]), _dptr(out["obs_cond"]),
+                               _dptr(out["nom_cond"])) if diagnostics else (None, None, None, None)))
     if rc != 0:
         raise ValueError("oracle step rejected its arguments")
     out["u0"] = out["V_plus"][0].copy()

@@ -53,7 +53,7 @@ Geometry geometry(const mppi_params* p) {
     g.block = (g.spb * p->M + 63) / 64 * 64;
     g.n_nom_wg = (p->K + g.block - 1) / g.block;
     g.G = (p->K + kPartBlock - 1) / kPartBlock;
-    g.lds_rollout = 16 * (size_t)p->n_obs + 8 * (size_t)g.spb * p->T + 4 * (2 * (size_t)g.spb * p->M + g.spb);
+    g.lds_rollout = 8 * (size_t)g.spb * p->T + 4 * (2 * (size_t)g.spb * p->M + g.spb);
     g.lds_merge = 4 * ((size_t)g.G + 2 * (size_t)p->T);
     return g;
 }
@@ -72,7 +72,7 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, u, S, cvar, S_tilde, w_hat, L, part, u0, total;
+    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, total;
 };
 
 Layout layout(const mppi_params* p) {
@@ -80,6 +80,7 @@ Layout layout(const mppi_params* p) {
     Layout l;
     size_t o = 0;
     l.obs = o;     o += align_up(16 * (size_t)(p->n_obs > 0 ? p->n_obs : 1));
+    l.tab = o;     o += align_up(16 * (size_t)(p->n_obs > 0 ? (p->n_obs + 7) / 8 * 8 : 8));
     l.u = o;       o += align_up(8 * (size_t)p->K * p->T);
     l.S = o;       o += align_up(4 * (size_t)p->K);
     l.cvar = o;    o += align_up(4 * (size_t)p->K);
@@ -163,7 +164,7 @@ mppi_status mppi_validate(const mppi_params* p) {
     if ((int64_t)p->K * p->M > (int64_t)INT32_MAX) return fail(MPPI_EUNSUPPORTED, "K * M exceeds 2^31 - 1");
     const Geometry g = geometry(p);
     if (g.lds_rollout > kMaxLdsBytes)
-        return fail(MPPI_EUNSUPPORTED, "rollout LDS need %zu B exceeds %zu B (reduce T or n_obs)", g.lds_rollout,
+        return fail(MPPI_EUNSUPPORTED, "rollout LDS need %zu B exceeds %zu B (reduce T or M)", g.lds_rollout,
                     kMaxLdsBytes);
     if (g.lds_merge > kMaxLdsBytes)
         return fail(MPPI_EUNSUPPORTED, "merge LDS need %zu B exceeds %zu B (reduce K or T)", g.lds_merge,
@@ -313,6 +314,7 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
 
     ramppi::StepBuffers bufs;
     bufs.obs = reinterpret_cast<const float4*>(h->ws + h->l.obs);
+    bufs.tab = reinterpret_cast<float4*>(h->ws + h->l.tab);
     bufs.V = V_dev;
     bufs.Vout = V_dev;
     bufs.u = reinterpret_cast<float2*>(h->ws + h->l.u);
@@ -324,15 +326,14 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     bufs.part = reinterpret_cast<float*>(h->ws + h->l.part);
     bufs.u0 = reinterpret_cast<float*>(h->ws + h->l.u0);
 
-    hipEvent_t ev_mid = nullptr, ev_end = nullptr;
+    hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_end = nullptr;
     if (h->timing && h->n_timed < kMaxTimedSteps) {
         hipEvent_t* e3 = &h->ev[3 * (size_t)h->n_timed];
-        hipError_t e = hipEventRecord(e3[0], s);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        ev_start = e3[0];
         ev_mid = e3[1];
         ev_end = e3[2];
     }
-    hipError_t e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_merge, s, ev_mid);
+    hipError_t e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_merge, s, ev_start, ev_mid);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     if (ev_end) {
         e = hipEventRecord(ev_end, s);

@@ -51,13 +51,14 @@ __device__ __forceinline__ float uniform01(uint32_t r) {
     return __fmaf_rn((float)(r >> 9), 0x1p-23f, 0x1p-24f);
 }
 
-// Two standard normals from two uniforms (Box-Muller).
+// Two standard normals from two uniforms (Box-Muller).  The hardware
+// logarithm is base 2 and the hardware sine / cosine take revolutions, so
+// -2 ln u0 = -2 ln(2) log2(u0) and cos(2 pi u1) is v_cos_f32(u1).  u0 lies in
+// [2^-24, 1), a normal number, and u1 in (0, 1), inside the hardware range.
 __device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
-    const float rad = sqrtf(-2.0f * logf(u0));
-    float s, c;
-    sincospif(2.0f * u1, &s, &c);
-    z0 = rad * c;
-    z1 = rad * s;
+    const float rad = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u0));
+    z0 = rad * __builtin_amdgcn_cosf(u1);
+    z1 = rad * __builtin_amdgcn_sinf(u1);
 }
 
 __device__ __forceinline__ float4 normals4(uint4 r) {
@@ -95,9 +96,13 @@ struct State {
 };
 
 // Forward-Euler bicycle step: da = dt a, kappa = tan(delta) / wheelbase.
+// The heading is turned into revolutions and reduced to [-1/2, 1/2] for the
+// hardware sine and cosine.
 __device__ __forceinline__ void bicycle_step(State& s, float da, float kappa, float dt) {
-    float sn, cs;
-    sincosf(s.psi, &sn, &cs);
+    float r = s.psi * 0.159154943091895335769f;
+    r = r - rintf(r);
+    const float sn = __builtin_amdgcn_sinf(r);
+    const float cs = __builtin_amdgcn_cosf(r);
     const float dv = dt * s.v;
     s.x = __fmaf_rn(dv, cs, s.x);
     s.y = __fmaf_rn(dv, sn, s.y);
@@ -116,7 +121,7 @@ __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s)
     const float gy = Y * c.g_b;   // 2 Y / b^2
     const float gn2 = fmaxf(__fmaf_rn(gx, gx, gy * gy), 1e-24f);
     const float dv = s.v - c.v_ref;
-    float q = __fmaf_rn(c.c_v * dv, dv, c.c_dev * (G * G / gn2));
+    float q = __fmaf_rn(c.c_v * dv, dv, c.c_dev * (G * G * __builtin_amdgcn_rcpf(gn2)));
     if (c.use_bdry) {
         const float e = G * rsqrtf(gn2);
         const float d = c.hw - fabsf(e);
@@ -126,23 +131,36 @@ __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s)
     return q;
 }
 
+// Eight obstacle-table entries, read together (scalar loads of 128 bytes).
+struct __attribute__((aligned(128))) ObstacleOct {
+    float4 o[8];
+};
+
 // Number of obstacle discs strictly containing the point (Eq. 22 summed over
-// obstacles).  tab[i] = (-2 cx, -2 cy, cx^2 + cy^2 - r^2) in the local frame,
-// so that |p - c|^2 - r^2 = |p|^2 + tab.x px + tab.y py + tab.z.
-__device__ __forceinline__ int obstacle_hits(const float4* __restrict__ tab, int n_obs, float px, float py) {
-    const float neg_rho = -__fmaf_rn(px, px, py * py);
+// obstacles).  tab[i] = (-2 cx, -2 cy, r^2 - cx^2 - cy^2, 0) in the local
+// frame, so the point p is inside disc i iff |p|^2 + tab.x px + tab.y py <
+// tab.z.  The table is read with wave-uniform addresses (scalar loads into
+// SGPRs); per obstacle the test is two FMAs and one compare whose lane mask is
+// OR-ed into a wave-wide hit mask, and only a group of discs that some lane
+// of the wave is inside is counted lane by lane (from the sign of the same
+// difference, so both paths take the same decision).  The table is padded to
+// a multiple of 8 entries that no point can hit (tab.z = -inf).
+__device__ __forceinline__ int obstacle_hits(const ObstacleOct* __restrict__ tab, int n_oct, float px, float py) {
+    const float rho = __fmaf_rn(px, px, py * py);
     int cnt = 0;
-    int i = 0;
-    for (; i + 4 <= n_obs; i += 4) {
-        const float4 o0 = tab[i], o1 = tab[i + 1], o2 = tab[i + 2], o3 = tab[i + 3];
-        cnt += (__fmaf_rn(o0.x, px, __fmaf_rn(o0.y, py, o0.z)) < neg_rho);
-        cnt += (__fmaf_rn(o1.x, px, __fmaf_rn(o1.y, py, o1.z)) < neg_rho);
-        cnt += (__fmaf_rn(o2.x, px, __fmaf_rn(o2.y, py, o2.z)) < neg_rho);
-        cnt += (__fmaf_rn(o3.x, px, __fmaf_rn(o3.y, py, o3.z)) < neg_rho);
-    }
-    for (; i < n_obs; ++i) {
-        const float4 o = tab[i];
-        cnt += (__fmaf_rn(o.x, px, __fmaf_rn(o.y, py, o.z)) < neg_rho);
+    for (int i = 0; i < n_oct; ++i) {
+        const ObstacleOct g = tab[i];
+        float s[8];
+        uint64_t hit = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            s[j] = __fmaf_rn(g.o[j].x, px, __fmaf_rn(g.o[j].y, py, rho));
+            hit |= __builtin_amdgcn_ballot_w64(s[j] < g.o[j].z);
+        }
+        if (hit) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cnt += (int)(__float_as_uint(s[j] - g.o[j].z) >> 31);
+        }
     }
     return cnt;
 }

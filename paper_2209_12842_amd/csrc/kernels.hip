@@ -1,12 +1,13 @@
 // Kernels of the RA-MPPI control step for gfx950.
 //
-// One step is three launches on the caller's stream:
+// One step is four launches on the caller's stream:
+//   k_obstacle_frame  the obstacle table in the frame of the start position;
 //   k_rollout   nominal workgroups (one lane per sample k: sampled controls,
 //               nominal rollout, cost S; Eq. 1-3) and disturbed workgroups
 //               (one lane per pair (k, m): disturbed rollout and risk cost L,
 //               Eq. 6, 9; then scaling and the CVaR tail mean per sample,
-//               Eq. 10-13, 18-19), with the obstacle table and the sample's
-//               controls staged in LDS;
+//               Eq. 10-13, 18-19), with the sample's controls staged in LDS
+//               and the obstacle table read through scalar loads;
 //   k_partials  per 256-sample chunk: S~ = S + J_C (Eq. 14-16), the chunk's
 //               minimum, its weight sum and its weighted control sums (Eq. 17);
 //   k_merge     one workgroup: log-sum-exp merge of the chunks, V+ (Eq. 4),
@@ -17,22 +18,29 @@
 
 namespace ramppi {
 
+// Obstacle table of one step in the local frame centred on the start
+// position: tab[i] = (-2 cx, -2 cy, r^2 - cx^2 - cy^2, 0) for i < n_obs, and
+// entries up to the next multiple of 8 that no point can hit (tab.z = -inf).
+__global__ void __launch_bounds__(256) k_obstacle_frame(const float4* __restrict__ obs, int n_obs, float fx,
+                                                        float fy, float4* __restrict__ tab) {
+    const int n_pad = (n_obs + 7) & ~7;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x) {
+        if (i < n_obs) {
+            const float4 o = obs[i];  // cx, cy, r, unused
+            const float cx = o.x - fx;
+            const float cy = o.y - fy;
+            tab[i] = make_float4(-2.0f * cx, -2.0f * cy, __fmaf_rn(o.z, o.z, -__fmaf_rn(cx, cx, cy * cy)), 0.0f);
+        } else {
+            tab[i] = make_float4(0.0f, 0.0f, -__builtin_inff(), 0.0f);
+        }
+    }
+}
+
 // LDS layout of k_rollout (dynamic shared memory, in this order):
-//   float4 tab[n_obs]     obstacle table in the local frame
 //   float2 ctl[spb * T]   (dt a, tan(delta) / wheelbase) of the WG's samples
 //   float  vals[spb * M]  risk costs of the WG's samples
 //   float  tail[spb * M]  tail slots (descending)
 //   float  means[spb]     mean risk cost per sample (risk scaling)
-__device__ __forceinline__ void build_obstacle_table(const StepConst& c, const float4* __restrict__ obs,
-                                                     float4* tab) {
-    for (int i = threadIdx.x; i < c.n_obs; i += blockDim.x) {
-        const float4 o = obs[i];  // cx, cy, r, unused
-        const float cx = o.x - c.fx;
-        const float cy = o.y - c.fy;
-        tab[i] = make_float4(-2.0f * cx, -2.0f * cy, __fmaf_rn(cx, cx, __fmaf_rn(cy, cy, -o.z * o.z)), 0.0f);
-    }
-}
-
 // Scal, Max and Average of Algorithm 1 for the spb samples of a workgroup.
 // vals holds the raw risk costs (thread tid owns slot tid for tid < spb * M);
 // returns the CVaR in the m == 0 lane of each sample.
@@ -63,23 +71,20 @@ __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* 
     return cv;
 }
 
-__global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __restrict__ obs,
+__global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct* __restrict__ tab,
                                                   const float* __restrict__ V, float2* __restrict__ u_out,
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
                                                   float* __restrict__ L_out) {
-    extern __shared__ float4 smem[];
-    float4* tab = smem;
-    float2* ctl = reinterpret_cast<float2*>(tab + c.n_obs);
+    extern __shared__ float2 smem[];
+    float2* ctl = smem;
     float* vals = reinterpret_cast<float*>(ctl + (size_t)c.spb * c.T);
     float* tail = vals + c.spb * c.M;
     float* means = tail + c.spb * c.M;
-
-    build_obstacle_table(c, obs, tab);
     const int tid = threadIdx.x;
+    const int n_oct = (c.n_obs + 7) >> 3;
 
     if ((int)blockIdx.x < c.n_nom_wg) {
         // ---- nominal rollouts: one lane per sample ----
-        __syncthreads();
         const int k = blockIdx.x * blockDim.x + tid;
         if (k >= c.K) return;
         State s{0.0f, 0.0f, c.psi0, c.v0};
@@ -89,7 +94,7 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __r
             const float2 u = sample_control(c, V, k, t);
             u_out[(size_t)t * c.K + k] = u;
             acc += smooth_cost(c, s);
-            cnt += obstacle_hits(tab, c.n_obs, s.x, s.y);
+            cnt += obstacle_hits(tab, n_oct, s.x, s.y);
             if (c.use_ctrl) {
                 const float term = __fmaf_rn(V[2 * t] * c.inv_var0, u.x, V[2 * t + 1] * c.inv_var1 * u.y);
                 ctrl = __fmaf_rn(c.gamma, term, ctrl);
@@ -131,7 +136,7 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __r
         int cnt = 0;
         for (int t = 0; t < T; ++t) {
             acc += smooth_cost(c, s);
-            cnt += obstacle_hits(tab, c.n_obs, s.x, s.y);
+            cnt += obstacle_hits(tab, n_oct, s.x, s.y);
             if (t + 1 < T) {  // the last draw cannot reach the risk cost
                 const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
                 const float4 z = normals4(r);
@@ -303,10 +308,14 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
 // ---- launchers ----
 
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
-                       size_t lds_merge, hipStream_t stream, hipEvent_t ev_mid) {
+                       size_t lds_merge, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
     const int n_dist_wg = (c.K + c.spb - 1) / c.spb;
-    hipLaunchKernelGGL(k_rollout, dim3(c.n_nom_wg + n_dist_wg), dim3(block), lds_rollout, stream, c, b.obs, b.V,
-                       b.u, b.S, b.cvar, b.L);
+    if (c.n_obs > 0)
+        hipLaunchKernelGGL(k_obstacle_frame, dim3((c.n_obs + 255) / 256), dim3(256), 0, stream, b.obs, c.n_obs,
+                           c.fx, c.fy, b.tab);
+    if (ev_start) (void)hipEventRecord(ev_start, stream);
+    hipLaunchKernelGGL(k_rollout, dim3(c.n_nom_wg + n_dist_wg), dim3(block), lds_rollout, stream, c,
+                       reinterpret_cast<const ObstacleOct*>(b.tab), b.V, b.u, b.S, b.cvar, b.L);
     if (ev_mid) (void)hipEventRecord(ev_mid, stream);
     hipLaunchKernelGGL(k_partials, dim3(G), dim3(256), 0, stream, c, b.S, b.cvar, b.u, b.S_tilde, b.part);
     hipLaunchKernelGGL(k_merge, dim3(1), dim3(256), lds_merge, stream, c, G, b.part, b.S_tilde, b.Vout, b.u0,

@@ -12,6 +12,7 @@ namespace ramppi {
 // Device buffers of one step (all inside the caller's workspace except V).
 struct StepBuffers {
     const float4* obs;  // n_obs x (cx, cy, r, 0)
+    float4* tab;        // n_obs obstacle table in the local frame
     const float* V;     // T x 2, the mean sequence (read by k_rollout)
     float* Vout;        // T x 2, V+ (written by k_merge; the same memory as V)
     float2* u;          // T x K sampled controls, time-major
@@ -25,7 +26,7 @@ struct StepBuffers {
 };
 
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
-                       size_t lds_merge, hipStream_t stream, hipEvent_t ev_mid);
+                       size_t lds_merge, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_normals(uint64_t seed, const uint32_t* ctr, float* out, int64_t n, hipStream_t stream);
 hipError_t launch_cvar(const float* L, int K, int M, int spb, int block, int n_tail, int scale_risk, float B,
