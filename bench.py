@@ -52,8 +52,8 @@ def model_bytes(p: dict, n_obs: int) -> float:
 def plant_step(x, u, dt, wb, w):
     """Host FP64 plant: the nominal bicycle plus an additive disturbance."""
     px, py, psi, v = x
-    return np.array([px + dt * v * math.cos(psi), py + dt * v * math.sin(psi),
-                     psi + dt * v * math.tan(u[1]) / wb, v + dt * u[0]]) + w
+    return [px + dt * v * math.cos(psi) + w[0], py + dt * v * math.sin(psi) + w[1],
+            psi + dt * v * math.tan(float(u[1])) / wb + w[2], v + dt * float(u[0]) + w[3]]
 
 
 def cpu_baseline(world: dict, budget_s: float = 10.0) -> dict:
@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy a MIB-sized device buffer 3 times (a plain copy kernel of "
+                         "known size for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -106,13 +109,14 @@ def main():
     V = ctl.new_V(world["V0"])
     dt32, wb32 = float(np.float32(p["dt"])), float(np.float32(p["wheelbase"]))
     sw = np.sqrt(np.float32(p["sigma_w"]).astype(np.float64))
-    rng = np.random.default_rng(12345)
-    x = np.asarray(world["x0"], dtype=np.float64)
+    n_total = args.warmup + args.steps
+    plant_w = (np.random.default_rng(12345).standard_normal((n_total, 4)) * sw).tolist()
+    x = [float(v) for v in world["x0"]]
 
     def one_step(j):
         nonlocal x
-        u0 = ctl.step(x.astype(np.float32), V, j, want_u0=True)
-        x = plant_step(x, u0.astype(np.float64), dt32, wb32, sw * rng.standard_normal(4))
+        u0 = ctl.step(x, V, j, want_u0=True)
+        x = plant_step(x, u0, dt32, wb32, plant_w[j])
         return u0
 
     for j in range(args.warmup):
@@ -130,7 +134,7 @@ def main():
     elapsed = time.perf_counter() - t0
     roll_ms, upd_ms, n_timed = ctl.timing_read()
     ctl.timing_enable(False)
-    assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(x))
+    assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(np.asarray(x)))
 
     steps_per_call = K * M * T
     value = steps_per_call * args.steps / elapsed
@@ -159,6 +163,14 @@ def main():
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
                      "kernel": "k_rollout", "model_flops_per_launch": flops},
     }
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = n
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(world)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

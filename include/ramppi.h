@@ -46,6 +46,14 @@ typedef enum {
     MPPI_EUNSUPPORTED = -4
 } mppi_status;
 
+/* Disturbance forms of the disturbed model x~' = F(x~, u) + w (Eq. 6-7). */
+enum {
+    MPPI_NOISE_GAUSSIAN = 0,      /* w = sqrt(diag sigma_w) z, z standard normal */
+    MPPI_NOISE_UNIFORM = 1,       /* w_i ~ U[-h_i, h_i], h_i = sqrt(3 sigma_w_i) (same covariance) */
+    MPPI_NOISE_IMPULSE = 2        /* with probability jump_prob, a jump of length jump_size in a
+                                     uniformly random (x, y) direction; otherwise zero */
+};
+
 enum {
     MPPI_F_DEBUG = 1u,            /* also write L (K x M) and normalised weights */
     MPPI_F_SHIFT = 2u,            /* V <- V+ shifted left by one step, last repeated */
@@ -77,6 +85,8 @@ enum {
  *                half width; e is the signed Sampson distance to it.
  *   seed         Philox4x32-10 key (low word, high word).
  *   flags        MPPI_F_* bits.
+ *   noise_kind   MPPI_NOISE_*; jump_prob in [0, 1] and jump_size >= 0 are read
+ *                by the impulse form only.
  */
 typedef struct {
     int32_t K, T, M, n_obs;
@@ -89,6 +99,8 @@ typedef struct {
     float track[5];
     uint64_t seed;
     uint32_t flags;
+    uint32_t noise_kind;
+    float jump_prob, jump_size;
 } mppi_params;
 
 /* Device pointers into the workspace, valid while the handle lives.
@@ -128,7 +140,7 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
  *             (seed, step_idx, x0, V) reproduces the same result bit for bit.
  *   u0_host   NULL, or host memory for 2 floats: the first command of V+
  *             before any shift.  When set, the call waits for the step.
- * Enqueues four kernels on `stream` and returns. */
+ * Enqueues three kernels on `stream` and returns. */
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
 
@@ -144,7 +156,7 @@ const char *mppi_last_error(void);
 mppi_status mppi_debug_view(const mppi_handle *h, mppi_debug_ptrs *out);
 
 /* Kernel timing with HIP events recorded on the step's stream around the
- * rollout kernel and around the two update kernels.  enable != 0 starts
+ * rollout kernel and around the update kernel.  enable != 0 starts
  * recording (and clears earlier records); mppi_timing_read waits for the
  * recorded steps, returns the summed milliseconds and the step count, and
  * clears the records.  At most 4096 steps are kept. */

@@ -57,6 +57,8 @@ class _Params(ctypes.Structure):
         ("track", ctypes.c_double * 5),
         ("seed", ctypes.c_uint64),
         ("shift", ctypes.c_int32),
+        ("noise_kind", ctypes.c_int32),
+        ("jump_prob", ctypes.c_double), ("jump_size", ctypes.c_double),
     ]
 
 
@@ -80,6 +82,8 @@ def _load():
         lib.orc_normals4.argtypes = [P(ctypes.c_uint32), ctypes.c_uint64, P(D)]
         lib.orc_normals_batch.argtypes = [P(ctypes.c_uint32), ctypes.c_int64, ctypes.c_uint64, P(D)]
         lib.orc_dynamics.argtypes = [P(D), P(D), D, D, P(D)]
+        lib.orc_disturbance.argtypes = [P(_Params), P(ctypes.c_uint32), P(D)]
+        lib.orc_disturbance_batch.argtypes = [P(_Params), P(ctypes.c_uint32), ctypes.c_int64, P(D)]
         lib.orc_track_terms.argtypes = [P(_Params), P(D), P(D), P(D)]
         lib.orc_boundary_cost.argtypes = [D]
         lib.orc_boundary_cost.restype = D
@@ -158,6 +162,9 @@ def make_params(p: dict, n_obs: int) -> _Params:
         s.track[i] = _f32(p["track"][i])
     s.seed = int(p["seed"]) & 0xFFFFFFFFFFFFFFFF
     s.shift = 1 if p.get("shift", False) else 0
+    s.noise_kind = int(p.get("noise_kind", 0))
+    s.jump_prob = _f32(p.get("jump_prob", 0.0))
+    s.jump_size = _f32(p.get("jump_size", 0.0))
     return s
 
 
@@ -209,6 +216,15 @@ def normals_batch(ctr: np.ndarray, seed: int) -> np.ndarray:
     z = np.empty((c.shape[0], 4))
     _load().orc_normals_batch(_u32ptr(c), c.shape[0], int(seed) & 0xFFFFFFFFFFFFFFFF, _dptr(z))
     return z
+
+
+def disturbance_batch(p: dict, ctr: np.ndarray) -> np.ndarray:
+    """Disturbances w (n x 4) of n Philox counters under the form p['noise_kind']."""
+    s = make_params(p, 0)
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    w = np.empty((c.shape[0], 4))
+    _load().orc_disturbance_batch(ctypes.byref(s), _u32ptr(c), c.shape[0], _dptr(w))
+    return w
 
 
 # --------------------------------------------------------- model pieces ----

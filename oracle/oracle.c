@@ -49,6 +49,8 @@ typedef struct {
     double track[5];             /* ellipse centre ox, oy, semi-axes a, b, half width */
     uint64_t seed;               /* Philox key = (low 32 bits, high 32 bits) */
     int32_t shift;               /* non-zero: shift the updated sequence by one step */
+    int32_t noise_kind;          /* disturbance form: 0 Gaussian, 1 uniform, 2 impulse */
+    double jump_prob, jump_size; /* impulse form: probability per step, jump length */
 } orc_params;
 
 /* ------------------------------------------------------------------------ */
@@ -461,14 +463,51 @@ double orc_nominal_cost(const orc_params *p, const double *obs, const double x0[
     return S;
 }
 
+/* Disturbance w_t of one (sample, draw, step) counter.  The method accepts
+ * any zero-mean additive form (Eq. 6-7); the paper's experiments use three,
+ * read here as:
+ *   0 Gaussian: w = sqrt(diag Sigma_w) z, z standard normal (Box-Muller);
+ *   1 uniform:  w_i ~ U[-h_i, h_i] with h_i = sqrt(3 Sigma_w,i), i.e. the same
+ *               covariance as the Gaussian form (w_i = h_i (2 u_i - 1));
+ *   2 impulse:  with probability jump_prob a jump of length jump_size in a
+ *               uniformly random direction of the (x, y) plane, else zero
+ *               (u_0 < jump_prob decides, angle 2 pi u_1). */
+void orc_disturbance(const orc_params *p, const uint32_t ctr[4], double w[4])
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    if (p->noise_kind == 0) {
+        double z[4];
+        orc_normals4(ctr, p->seed, z);
+        for (int i = 0; i < 4; ++i) w[i] = sqrt(p->sigma_w[i]) * z[i];
+        return;
+    }
+    uint32_t key[2] = { (uint32_t)(p->seed & 0xFFFFFFFFu), (uint32_t)(p->seed >> 32) };
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    if (p->noise_kind == 1) {
+        for (int i = 0; i < 4; ++i) w[i] = sqrt(3.0 * p->sigma_w[i]) * (2.0 * orc_uniform(r[i]) - 1.0);
+        return;
+    }
+    w[0] = w[1] = w[2] = w[3] = 0.0;
+    if (orc_uniform(r[0]) < p->jump_prob) {
+        double th = two_pi * orc_uniform(r[1]);
+        w[0] = p->jump_size * cos(th);
+        w[1] = p->jump_size * sin(th);
+    }
+}
+
+/* Batch form for the distribution pins: n counters -> n x 4 disturbances. */
+void orc_disturbance_batch(const orc_params *p, const uint32_t *ctr, int64_t n, double *w)
+{
+    for (int64_t i = 0; i < n; ++i) orc_disturbance(p, ctr + 4 * i, w + 4 * i);
+}
+
 /* Disturbed rollout of draw m of sample k and its risk cost L (Eq. 6, 9):
- * x~_{t+1} = F(x~_t, u_t) + w_t with w_t = sqrt(diag Sigma_w) * z (additive
+ * x~_{t+1} = F(x~_t, u_t) + w_t with w_t from orc_disturbance (additive
  * zero-mean noise, so that F = E[F~] as Eq. 7 requires); l = q. */
 double orc_disturbed_cost(const orc_params *p, const double *obs, const double x0[4],
                           const double *uk, int k, int m, uint32_t step_idx, double *margin, double *cond)
 {
-    double sw[4];
-    for (int i = 0; i < 4; ++i) sw[i] = sqrt(p->sigma_w[i]);
     double x[4] = { x0[0], x0[1], x0[2], x0[3] }, xn[4];
     double L = 0.0, mg = INFINITY, cd = INFINITY;
     for (int t = 0; t < p->T; ++t) {
@@ -482,10 +521,10 @@ double orc_disturbed_cost(const orc_params *p, const double *obs, const double x
             if (r < cd) cd = r;
         }
         uint32_t ctr[4] = { (uint32_t)t, (uint32_t)m, (uint32_t)k, step_idx };
-        double z[4];
-        orc_normals4(ctr, p->seed, z);
+        double w[4];
+        orc_disturbance(p, ctr, w);
         orc_dynamics(x, uk + 2 * t, p->dt, p->wheelbase, xn);
-        for (int i = 0; i < 4; ++i) x[i] = xn[i] + sw[i] * z[i];
+        for (int i = 0; i < 4; ++i) x[i] = xn[i] + w[i];
     }
     if (margin) *margin = mg;
     if (cond) *cond = cd;

@@ -43,6 +43,8 @@ class Params(ctypes.Structure):
         ("track", ctypes.c_float * 5),
         ("seed", ctypes.c_uint64),
         ("flags", ctypes.c_uint32),
+        ("noise_kind", ctypes.c_uint32),
+        ("jump_prob", ctypes.c_float), ("jump_size", ctypes.c_float),
     ]
 
 
@@ -122,6 +124,9 @@ def make_params(p: dict, n_obs: int, flags: int = 0) -> Params:
         s.track[i] = float(p["track"][i])
     s.seed = int(p["seed"]) & 0xFFFFFFFFFFFFFFFF
     s.flags = int(flags) | (MPPI_F_SHIFT if p.get("shift", False) else 0)
+    s.noise_kind = int(p.get("noise_kind", 0))
+    s.jump_prob = float(p.get("jump_prob", 0.0))
+    s.jump_size = float(p.get("jump_size", 0.0))
     return s
 
 
@@ -165,6 +170,8 @@ class Controller:
                                 ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                 ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(self._h)))
         self.K, self.T, self.M = self.p.K, self.p.T, self.p.M
+        self._x0 = (ctypes.c_float * 4)()
+        self._step_fn = L.mppi_step
 
     def new_V(self, V0=None):
         """A T x 2 float32 mean sequence on the controller's device."""
@@ -180,10 +187,11 @@ class Controller:
         torch = _torch()
         if not (V.is_cuda and V.dtype == torch.float32 and V.is_contiguous() and V.numel() == 2 * self.T):
             raise ValueError("V must be a contiguous float32 CUDA tensor with T x 2 elements")
-        x = (ctypes.c_float * 4)(*[float(v) for v in np.asarray(x0, dtype=np.float32).reshape(4)])
+        x = self._x0
+        x[0], x[1], x[2], x[3] = (float(v) for v in x0)
         u0p = self._u0 if want_u0 else None
-        check(lib().mppi_step(self._h, x, ctypes.c_void_p(V.data_ptr()), int(step_idx) & 0xFFFFFFFF, u0p,
-                              ctypes.c_void_p(_stream_ptr(V.device))))
+        check(self._step_fn(self._h, x, V.data_ptr(), int(step_idx) & 0xFFFFFFFF, u0p,
+                            torch.cuda.current_stream(V.device).cuda_stream))
         if want_u0:
             return np.array([self._u0[0], self._u0[1]], dtype=np.float32)
         return None

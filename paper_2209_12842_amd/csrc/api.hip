@@ -44,7 +44,7 @@ bool finite(float v) { return std::isfinite(v); }
 // Launch geometry derived from the sizes.
 struct Geometry {
     int spb, block, n_nom_wg, G;
-    size_t lds_rollout, lds_merge;
+    size_t lds_rollout, lds_update;
 };
 
 Geometry geometry(const mppi_params* p) {
@@ -54,7 +54,7 @@ Geometry geometry(const mppi_params* p) {
     g.n_nom_wg = (p->K + g.block - 1) / g.block;
     g.G = (p->K + kPartBlock - 1) / kPartBlock;
     g.lds_rollout = 8 * (size_t)g.spb * p->T + 4 * (2 * (size_t)g.spb * p->M + g.spb);
-    g.lds_merge = 4 * ((size_t)g.G + 2 * (size_t)p->T);
+    g.lds_update = ramppi::update_lds_bytes(p->T, g.G);
     return g;
 }
 
@@ -72,7 +72,7 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, total;
+    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, total;
 };
 
 Layout layout(const mppi_params* p) {
@@ -89,6 +89,7 @@ Layout layout(const mppi_params* p) {
     l.L = o;       o += align_up(4 * (size_t)p->K * p->M);
     l.part = o;    o += align_up(4 * (size_t)g.G * (2 + 2 * (size_t)p->T));
     l.u0 = o;      o += align_up(8);
+    l.counter = o; o += align_up(4);
     l.total = o;
     return l;
 }
@@ -110,7 +111,8 @@ struct mppi_handle {
     Layout l;
     int n_tail, n_warm, device;
     char* ws;
-    float* u0_pinned;
+    float* u0_pinned;      // mapped, coherent pinned host memory (2 floats)
+    float* u0_pinned_dev;  // its device address
     bool timing;
     std::vector<hipEvent_t> ev;  // 3 per timed step: start, after rollout, end
     int n_timed;
@@ -157,6 +159,9 @@ mppi_status mppi_validate(const mppi_params* p) {
     if (!(finite(p->track[2]) && p->track[2] > 0 && finite(p->track[3]) && p->track[3] > 0))
         return fail(MPPI_EINVAL, "track semi-axes must be finite and > 0");
     if (!(finite(p->track[4]) && p->track[4] >= 0)) return fail(MPPI_EINVAL, "track half width must be >= 0");
+    if (p->noise_kind > MPPI_NOISE_IMPULSE) return fail(MPPI_EINVAL, "unknown noise_kind %u", p->noise_kind);
+    if (!(p->jump_prob >= 0 && p->jump_prob <= 1)) return fail(MPPI_EINVAL, "jump_prob must lie in [0, 1]");
+    if (!(finite(p->jump_size) && p->jump_size >= 0)) return fail(MPPI_EINVAL, "jump_size must be finite and >= 0");
     if (p->M > MPPI_MAX_M) return fail(MPPI_EUNSUPPORTED, "M = %d exceeds %d", p->M, MPPI_MAX_M);
     if (p->n_obs > MPPI_MAX_OBS) return fail(MPPI_EUNSUPPORTED, "n_obs = %d exceeds %d", p->n_obs, MPPI_MAX_OBS);
     if (p->T > MPPI_MAX_T) return fail(MPPI_EUNSUPPORTED, "T = %d exceeds %d", p->T, MPPI_MAX_T);
@@ -166,8 +171,8 @@ mppi_status mppi_validate(const mppi_params* p) {
     if (g.lds_rollout > kMaxLdsBytes)
         return fail(MPPI_EUNSUPPORTED, "rollout LDS need %zu B exceeds %zu B (reduce T or M)", g.lds_rollout,
                     kMaxLdsBytes);
-    if (g.lds_merge > kMaxLdsBytes)
-        return fail(MPPI_EUNSUPPORTED, "merge LDS need %zu B exceeds %zu B (reduce K or T)", g.lds_merge,
+    if (g.lds_update > kMaxLdsBytes)
+        return fail(MPPI_EUNSUPPORTED, "update LDS need %zu B exceeds %zu B (reduce K or T)", g.lds_update,
                     kMaxLdsBytes);
     return MPPI_OK;
 }
@@ -208,10 +213,17 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     h->ws = static_cast<char*>(workspace_dev);
     h->timing = false;
     h->n_timed = 0;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->u0_pinned), 2 * sizeof(float), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->u0_pinned), 2 * sizeof(float),
+                                 hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "hipHostMalloc");
+    }
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&h->u0_pinned_dev), h->u0_pinned, 0);
+    if (e != hipSuccess) {
+        (void)hipHostFree(h->u0_pinned);
+        delete h;
+        return hip_fail(e, "hipHostGetDevicePointer");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<float> staged(4 * (size_t)(p->n_obs > 0 ? p->n_obs : 1), 0.0f);
@@ -221,6 +233,7 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
         staged[4 * i + 2] = obstacles_host[3 * i + 2];
     }
     e = hipMemcpyAsync(h->ws + l.obs, staged.data(), 16 * (size_t)p->n_obs, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.counter, 0, 4, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipHostFree(h->u0_pinned);
@@ -274,6 +287,15 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     c.sw1 = (float)std::sqrt((double)p.sigma_w[1]);
     c.sw2 = (float)std::sqrt((double)p.sigma_w[2]);
     c.sw3 = (float)std::sqrt((double)p.sigma_w[3]);
+    c.noise_kind = (int32_t)p.noise_kind;
+    if (p.noise_kind == MPPI_NOISE_UNIFORM) {  // half widths sqrt(3 sigma_w) in the sw slots
+        c.sw0 = (float)std::sqrt(3.0 * p.sigma_w[0]);
+        c.sw1 = (float)std::sqrt(3.0 * p.sigma_w[1]);
+        c.sw2 = (float)std::sqrt(3.0 * p.sigma_w[2]);
+        c.sw3 = (float)std::sqrt(3.0 * p.sigma_w[3]);
+    }
+    c.jump_prob = p.jump_prob;
+    c.jump_size = p.jump_size;
     c.gamma = p.gamma;
     c.use_ctrl = p.gamma != 0.0f;
     c.inv_var0 = c.use_ctrl ? (float)(1.0 / (double)p.sigma_eps[0]) : 0.0f;
@@ -325,6 +347,8 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     bufs.L = reinterpret_cast<float*>(h->ws + h->l.L);
     bufs.part = reinterpret_cast<float*>(h->ws + h->l.part);
     bufs.u0 = reinterpret_cast<float*>(h->ws + h->l.u0);
+    bufs.counter = reinterpret_cast<unsigned*>(h->ws + h->l.counter);
+    bufs.u0_host = u0_host ? h->u0_pinned_dev : nullptr;
 
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_end = nullptr;
     if (h->timing && h->n_timed < kMaxTimedSteps) {
@@ -333,7 +357,7 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         ev_mid = e3[1];
         ev_end = e3[2];
     }
-    hipError_t e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_merge, s, ev_start, ev_mid);
+    hipError_t e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_update, s, ev_start, ev_mid);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     if (ev_end) {
         e = hipEventRecord(ev_end, s);
@@ -341,8 +365,8 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         h->n_timed++;
     }
     if (u0_host) {
-        e = hipMemcpyAsync(h->u0_pinned, bufs.u0, 2 * sizeof(float), hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        // the update kernel stored the command into the mapped pinned buffer
+        e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "first-command readback");
         u0_host[0] = h->u0_pinned[0];
         u0_host[1] = h->u0_pinned[1];

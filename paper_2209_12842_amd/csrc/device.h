@@ -30,10 +30,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
                                                uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = c0 * kPhiloxM0;
-        const uint32_t hi0 = __umulhi(c0, kPhiloxM0);
-        const uint32_t lo1 = c2 * kPhiloxM1;
-        const uint32_t hi1 = __umulhi(c2, kPhiloxM1);
+        const uint64_t p0 = (uint64_t)c0 * kPhiloxM0;  // one v_mad_u64_u32 each
+        const uint64_t p1 = (uint64_t)c2 * kPhiloxM1;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -61,6 +61,13 @@ __device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float&
     z1 = rad * __builtin_amdgcn_sinf(u1);
 }
 
+// Disturbance of one (sample, draw, step) from its Philox words, in the form
+// selected at compile time: Gaussian sqrt(Sigma_w) z; uniform h (2u - 1) with
+// h = sqrt(3 Sigma_w); impulse: a jump of length jump_size at angle 2 pi u1 in
+// the (x, y) plane when u0 < jump_prob, otherwise zero.
+template <int kNoise>
+__device__ __forceinline__ float4 disturbance(const struct StepConst& c, uint4 r);
+
 __device__ __forceinline__ float4 normals4(uint4 r) {
     float4 z;
     box_muller(uniform01(r.x), uniform01(r.y), z.x, z.y);
@@ -78,7 +85,9 @@ struct StepConst {
     float dt, inv_wheelbase;
     float u_lo0, u_lo1, u_hi0, u_hi1;
     float se0, se1;      // control-noise standard deviations
-    float sw0, sw1, sw2, sw3;  // disturbance standard deviations
+    float sw0, sw1, sw2, sw3;  // disturbance scales: standard deviations (Gaussian) or half widths (uniform)
+    int32_t noise_kind;        // 0 Gaussian, 1 uniform, 2 impulse
+    float jump_prob, jump_size;
     float gamma, inv_var0, inv_var1;
     float A, B, C_u, lambda;
     float c_bdry, c_obs, c_dev, c_v, v_ref, c4, c5;
@@ -94,6 +103,23 @@ struct StepConst {
 struct State {
     float x, y, psi, v;  // position in the local frame
 };
+
+template <int kNoise>
+__device__ __forceinline__ float4 disturbance(const StepConst& c, uint4 r) {
+    if (kNoise == 0) {
+        const float4 z = normals4(r);
+        return make_float4(c.sw0 * z.x, c.sw1 * z.y, c.sw2 * z.z, c.sw3 * z.w);
+    } else if (kNoise == 1) {
+        return make_float4(c.sw0 * __fmaf_rn(2.0f, uniform01(r.x), -1.0f),
+                           c.sw1 * __fmaf_rn(2.0f, uniform01(r.y), -1.0f),
+                           c.sw2 * __fmaf_rn(2.0f, uniform01(r.z), -1.0f),
+                           c.sw3 * __fmaf_rn(2.0f, uniform01(r.w), -1.0f));
+    } else {
+        const float u1 = uniform01(r.y);
+        const float j = uniform01(r.x) < c.jump_prob ? c.jump_size : 0.0f;
+        return make_float4(j * __builtin_amdgcn_cosf(u1), j * __builtin_amdgcn_sinf(u1), 0.0f, 0.0f);
+    }
+}
 
 // Forward-Euler bicycle step: da = dt a, kappa = tan(delta) / wheelbase.
 // The heading is turned into revolutions and reduced to [-1/2, 1/2] for the

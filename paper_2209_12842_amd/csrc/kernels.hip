@@ -1,6 +1,6 @@
 // Kernels of the RA-MPPI control step for gfx950.
 //
-// One step is four launches on the caller's stream:
+// One step is three launches on the caller's stream:
 //   k_obstacle_frame  the obstacle table in the frame of the start position;
 //   k_rollout   nominal workgroups (one lane per sample k: sampled controls,
 //               nominal rollout, cost S; Eq. 1-3) and disturbed workgroups
@@ -8,10 +8,11 @@
 //               Eq. 6, 9; then scaling and the CVaR tail mean per sample,
 //               Eq. 10-13, 18-19), with the sample's controls staged in LDS
 //               and the obstacle table read through scalar loads;
-//   k_partials  per 256-sample chunk: S~ = S + J_C (Eq. 14-16), the chunk's
-//               minimum, its weight sum and its weighted control sums (Eq. 17);
-//   k_merge     one workgroup: log-sum-exp merge of the chunks, V+ (Eq. 4),
-//               the optional shift and the first command.
+//   k_update    per 256-sample chunk: S~ = S + J_C (Eq. 14-16), the chunk's
+//               minimum, weight sum and weighted control sums (Eq. 17); the
+//               last workgroup merges the chunks (log-sum-exp), forms V+
+//               (Eq. 4), the optional shift and the first command (also
+//               stored straight into mapped host memory when it is wanted).
 // Every reduction runs in a fixed order, so a step is bit-reproducible.
 #include "device.h"
 #include "launch.h"
@@ -71,6 +72,7 @@ __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* 
     return cv;
 }
 
+template <int kNoise>
 __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct* __restrict__ tab,
                                                   const float* __restrict__ V, float2* __restrict__ u_out,
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
@@ -139,13 +141,13 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct
             cnt += obstacle_hits(tab, n_oct, s.x, s.y);
             if (t + 1 < T) {  // the last draw cannot reach the risk cost
                 const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-                const float4 z = normals4(r);
+                const float4 w = disturbance<kNoise>(c, r);
                 const float2 cc = ck[t];
                 bicycle_step(s, cc.x, cc.y, c.dt);
-                s.x = __fmaf_rn(c.sw0, z.x, s.x);
-                s.y = __fmaf_rn(c.sw1, z.y, s.y);
-                s.psi = __fmaf_rn(c.sw2, z.z, s.psi);
-                s.v = __fmaf_rn(c.sw3, z.w, s.v);
+                s.x += w.x;
+                s.y += w.y;
+                s.psi += w.z;
+                s.v += w.w;
             }
         }
         L = __fmaf_rn(c.c_obs, (float)cnt, acc);
@@ -178,93 +180,120 @@ __device__ __forceinline__ float block_sum_256(float v, float* red) {
     return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Chunk partials: part[b] = (beta_b, Z_b, N_b[0..2T-1]) with
-// beta_b = min S~ over the chunk, Z_b = sum exp(-(S~ - beta_b)/lambda),
-// N_b[t] = sum exp(-(S~ - beta_b)/lambda) u_t.
-__global__ void __launch_bounds__(256) k_partials(StepConst c, const float* __restrict__ S,
-                                                  const float* __restrict__ cvar, const float2* __restrict__ u,
-                                                  float* __restrict__ S_tilde, float* __restrict__ part) {
-    __shared__ float wsh[256];
+// Weights and update (Eq. 14-17 and Eq. 4), one launch of G workgroups of
+// 256 threads, each owning a chunk of up to 256 samples:
+//  1. S~ = S + J_C per sample; the chunk's minimum beta_b, its weights
+//     exp(-(S~ - beta_b)/lambda) and their sum Z_b;
+//  2. the chunk's weighted control sums N_b[t] = sum_k w_k u_{k,t}, thread
+//     (t, part) summing a contiguous slice of the chunk, the slices then added
+//     in order;
+//  3. the partials (beta_b, Z_b, N_b) go to the workspace; the workgroup that
+//     finishes last (an acquire-release counter, which it resets for the next
+//     launch) merges them: beta = min beta_b, scale_b = exp(-(beta_b -
+//     beta)/lambda), V+ = sum_b scale_b N_b / sum_b scale_b Z_b, then writes V
+//     (shifted when asked), the first command and, in debug mode, w_hat.
+// No workgroup waits for another, and every sum runs in a fixed order.
+// LDS (dynamic): w[256] | slice sums [parts][2T] | scale[G] | vp[2T].
+__global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
+                                                const float* __restrict__ cvar, const float2* __restrict__ u,
+                                                float* __restrict__ S_tilde, float* part, unsigned* counter,
+                                                float* __restrict__ V, float* __restrict__ u0,
+                                                float* __restrict__ u0_host, float* __restrict__ w_hat) {
+    extern __shared__ float ush[];
     __shared__ float red[4];
+    __shared__ int is_last;
+    const int T = c.T, K = c.K;
+    float* wsh = ush;
+    float* psh = wsh + 256;
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
-    const int k = b * 256 + tid;
-    const int stride = 2 + 2 * c.T;
+    const int k0 = b * 256;
+    const int n = min(256, K - k0);
+    const int stride = 2 + 2 * T;
+
+    // 1. modified costs and chunk weights
     float st = __builtin_inff();
-    if (k < c.K) {
-        const float cv = cvar[k];
+    if (tid < n) {
+        const float cv = cvar[k0 + tid];
         const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
-        st = S[k] + jc;                                    // Eq. 16
-        S_tilde[k] = st;
+        st = S[k0 + tid] + jc;                             // Eq. 16
+        S_tilde[k0 + tid] = st;
     }
-    const float beta = block_min_256(st, red);
-    const float w = (k < c.K) ? expf(-(st - beta) / c.lambda) : 0.0f;
+    const float beta_b = block_min_256(st, red);
+    const float w = (tid < n) ? expf(-(st - beta_b) / c.lambda) : 0.0f;
     wsh[tid] = w;
-    const float Z = block_sum_256(w, red);  // also publishes wsh
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int t = wv; t < c.T; t += 4) {
+    const float Z_b = block_sum_256(w, red);  // also publishes wsh
+
+    // 2. weighted control sums over slices of the chunk
+    const int slice = (n + parts - 1) / parts;
+    for (int idx = tid; idx < T * parts; idx += 256) {
+        const int t = idx % T;
+        const int pr = idx / T;
+        const int ka = pr * slice, kb = min(n, ka + slice);
+        const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int kk = b * 256 + lane + 64 * j;
-            if (kk < c.K) {
-                const float2 uu = u[(size_t)t * c.K + kk];
-                const float ww = wsh[lane + 64 * j];
-                ax = __fmaf_rn(ww, uu.x, ax);
-                ay = __fmaf_rn(ww, uu.y, ay);
-            }
+        for (int k = ka; k < kb; ++k) {
+            const float2 uu = ut[k];
+            ax = __fmaf_rn(wsh[k], uu.x, ax);
+            ay = __fmaf_rn(wsh[k], uu.y, ay);
         }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0) {
-            part[(size_t)b * stride + 2 + 2 * t] = ax;
-            part[(size_t)b * stride + 3 + 2 * t] = ay;
-        }
+        psh[(size_t)pr * 2 * T + 2 * t] = ax;
+        psh[(size_t)pr * 2 * T + 2 * t + 1] = ay;
+    }
+    __syncthreads();
+    float* pb = part + (size_t)b * stride;
+    for (int j = tid; j < 2 * T; j += 256) {
+        float acc = 0.0f;
+        for (int pr = 0; pr < parts; ++pr) acc += psh[(size_t)pr * 2 * T + j];
+        pb[2 + j] = acc;
     }
     if (tid == 0) {
-        part[(size_t)b * stride] = beta;
-        part[(size_t)b * stride + 1] = Z;
+        pb[0] = beta_b;
+        pb[1] = Z_b;
     }
-}
 
-// Merge of the G chunk partials (one workgroup of 256 threads):
-// beta = min beta_b, scale_b = exp(-(beta_b - beta)/lambda),
-// V+ = sum_b scale_b N_b / sum_b scale_b Z_b.  LDS: scale[G], vp[2T].
-__global__ void __launch_bounds__(256) k_merge(StepConst c, int G, const float* __restrict__ part,
-                                               const float* __restrict__ S_tilde, float* __restrict__ V,
-                                               float* __restrict__ u0, float* __restrict__ w_hat) {
-    extern __shared__ float msh[];
-    float* scale = msh;
-    float* vp = msh + G;
-    __shared__ float red[4];
-    const int tid = threadIdx.x;
-    const int stride = 2 + 2 * c.T;
+    // 3. the last workgroup to finish merges every chunk
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (done == (unsigned)(G - 1));
+        if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+
+    float* scale = psh;               // reuses the slice sums
+    float* vp = scale + G;
     float bmin = __builtin_inff();
-    for (int b = tid; b < G; b += 256) bmin = fminf(bmin, part[(size_t)b * stride]);
+    for (int bb = tid; bb < G; bb += 256) bmin = fminf(bmin, part[(size_t)bb * stride]);
     const float beta = block_min_256(bmin, red);
     float z = 0.0f;
-    for (int b = tid; b < G; b += 256) {
-        const float sc = expf(-(part[(size_t)b * stride] - beta) / c.lambda);
-        scale[b] = sc;
-        z = __fmaf_rn(part[(size_t)b * stride + 1], sc, z);
+    for (int bb = tid; bb < G; bb += 256) {
+        const float sc = expf(-(part[(size_t)bb * stride] - beta) / c.lambda);
+        scale[bb] = sc;
+        z = __fmaf_rn(part[(size_t)bb * stride + 1], sc, z);
     }
     const float Z = block_sum_256(z, red);  // also publishes scale
     const float invZ = 1.0f / Z;
-    for (int j = tid; j < 2 * c.T; j += 256) {
+    for (int j = tid; j < 2 * T; j += 256) {
         float acc = 0.0f;
-        for (int b = 0; b < G; ++b) acc = __fmaf_rn(part[(size_t)b * stride + 2 + j], scale[b], acc);
+        for (int bb = 0; bb < G; ++bb) acc = __fmaf_rn(part[(size_t)bb * stride + 2 + j], scale[bb], acc);
         vp[j] = acc * invZ;
     }
     __syncthreads();
     const int shift = (c.flags & 2u) != 0;
-    for (int j = tid; j < 2 * c.T; j += 256) {
+    for (int j = tid; j < 2 * T; j += 256) {
         int src = j;
-        if (shift) src = min(j + 2, 2 * c.T - 2 + (j & 1));
+        if (shift) src = min(j + 2, 2 * T - 2 + (j & 1));
         V[j] = vp[src];
     }
-    if (tid < 2) u0[tid] = vp[tid];
+    if (tid < 2) {
+        u0[tid] = vp[tid];
+        if (u0_host) u0_host[tid] = vp[tid];  // mapped pinned host memory
+    }
     if (c.debug) {
-        for (int k = tid; k < c.K; k += 256) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
+        for (int k = tid; k < K; k += 256) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
     }
 }
 
@@ -307,19 +336,32 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
 
 // ---- launchers ----
 
+int update_parts(int T) { return T >= 256 ? 1 : 256 / T; }
+
+size_t update_lds_bytes(int T, int G) {
+    const size_t slices = (size_t)update_parts(T) * 2 * T;
+    const size_t merge = (size_t)G + 2 * (size_t)T;
+    return 4 * (256 + (slices > merge ? slices : merge));
+}
+
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
-                       size_t lds_merge, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
+                       size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
     const int n_dist_wg = (c.K + c.spb - 1) / c.spb;
     if (c.n_obs > 0)
         hipLaunchKernelGGL(k_obstacle_frame, dim3((c.n_obs + 255) / 256), dim3(256), 0, stream, b.obs, c.n_obs,
                            c.fx, c.fy, b.tab);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
-    hipLaunchKernelGGL(k_rollout, dim3(c.n_nom_wg + n_dist_wg), dim3(block), lds_rollout, stream, c,
-                       reinterpret_cast<const ObstacleOct*>(b.tab), b.V, b.u, b.S, b.cvar, b.L);
+    const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
+    const dim3 grid(c.n_nom_wg + n_dist_wg);
+    if (c.noise_kind == 1)
+        hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L);
+    else if (c.noise_kind == 2)
+        hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L);
+    else
+        hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L);
     if (ev_mid) (void)hipEventRecord(ev_mid, stream);
-    hipLaunchKernelGGL(k_partials, dim3(G), dim3(256), 0, stream, c, b.S, b.cvar, b.u, b.S_tilde, b.part);
-    hipLaunchKernelGGL(k_merge, dim3(1), dim3(256), lds_merge, stream, c, G, b.part, b.S_tilde, b.Vout, b.u0,
-                       b.w_hat);
+    hipLaunchKernelGGL(k_update, dim3(G), dim3(256), lds_update, stream, c, G, update_parts(c.T), b.S, b.cvar, b.u,
+                       b.S_tilde, b.part, b.counter, b.Vout, b.u0, b.u0_host, b.w_hat);
     return hipGetLastError();
 }
 

@@ -22,11 +22,15 @@ struct StepBuffers {
     float* w_hat;       // K
     float* L;           // K x M
     float* part;        // G x (2 + 2T)
+    unsigned* counter;  // chunks finished in the current update (0 between launches)
     float* u0;          // 2
+    float* u0_host;     // 2 floats of mapped pinned host memory, or null
 };
 
+int update_parts(int T);
+size_t update_lds_bytes(int T, int G);
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
-                       size_t lds_merge, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid);
+                       size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_normals(uint64_t seed, const uint32_t* ctr, float* out, int64_t n, hipStream_t stream);
 hipError_t launch_cvar(const float* L, int K, int M, int spb, int block, int n_tail, int scale_risk, float B,

@@ -28,9 +28,10 @@ def test_exports_every_declared_function(L):
 
 
 def test_params_struct_layout_matches_the_header():
-    # int32 x 4, 37 floats, then a uint64 (8-aligned) and a uint32: 160 bytes
-    assert ctypes.sizeof(Params) == 160
+    # int32 x 4, 37 floats, a uint64 (8-aligned), two uint32 and two floats: 168 bytes
+    assert ctypes.sizeof(Params) == 168
     assert Params.seed.offset == 144 and Params.flags.offset == 152
+    assert Params.noise_kind.offset == 156 and Params.jump_size.offset == 164
     assert Params.track.offset == 120
 
 
@@ -52,7 +53,8 @@ BAD = [
     dict(alpha=0.0), dict(alpha=1.0), dict(alpha=1.5), dict(lam=0.0), dict(lam=float("inf")),
     dict(gamma=-0.1), dict(gamma=2.0), dict(eta=-0.1), dict(eta=1.1), dict(A=-1.0), dict(B=-1.0),
     dict(C_u=float("nan")), dict(c_obs=float("inf")), dict(track=(0.0, 0.0, 0.0, 10.0, 3.0)),
-    dict(track=(0.0, 0.0, 15.0, 10.0, -1.0)),
+    dict(track=(0.0, 0.0, 15.0, 10.0, -1.0)), dict(noise_kind=3), dict(noise_kind=2, jump_prob=1.5),
+    dict(noise_kind=2, jump_size=-0.1),
 ]
 
 

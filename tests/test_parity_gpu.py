@@ -242,7 +242,8 @@ def test_plain_mppi_ignores_disturbances_on_device():
 
 @pytest.mark.parametrize("kw", [dict(K=1, M=1, T=1), dict(K=257, M=16, T=7), dict(K=33, M=7, T=5),
                                 dict(K=20, M=300, T=6), dict(K=5, M=1024, T=4), dict(K=300, M=64, T=3, n_obs=0),
-                                dict(K=64, M=16, T=9, eta=0.5, B=3.0, C_u=60.0, lam=20.0)])
+                                dict(K=64, M=16, T=9, eta=0.5, B=3.0, C_u=60.0, lam=20.0),
+                                dict(K=600, M=64, T=300, lam=50.0)])
 def test_edge_shapes(kw):
     kw = dict(kw)
     n_obs = kw.pop("n_obs", None)
@@ -257,3 +258,26 @@ def test_shift_and_first_command():
     p, obs, x0, V0 = _world("c1", shift=True)
     g, o, rep = _run(p, obs, x0, V0, 0, shift=True)
     assert np.abs(g["u0_host"] - o["u0"]).max() <= 1e-3
+
+
+@pytest.mark.parametrize("name,kw", [("c1", dict(noise_kind=1)),
+                                     ("c1", dict(noise_kind=2, jump_prob=0.02, jump_size=0.45)),
+                                     ("c2", dict(noise_kind=2, jump_prob=0.02, jump_size=0.45, K=512)),
+                                     ("p0", dict(noise_kind=1, M=64, K=256))])
+def test_step_disturbance_forms(name, kw):
+    # the paper's uniform and impulse disturbances (robustness experiments)
+    p, obs, x0, V0 = _world(name, **kw)
+    _run(p, obs, x0, W.random_V(p["T"], 8, scale=(1.0, 0.2)), 1, shift=bool(p.get("shift")))
+
+
+def test_disturbance_forms_stage_parity():
+    # the disturbed rollouts of a controller with zero control noise are pure
+    # functions of the disturbance draws: compare L against the oracle draw by draw
+    for kw in (dict(noise_kind=1), dict(noise_kind=2, jump_prob=0.3, jump_size=0.45)):
+        p, obs, x0, V0 = _world("c1", K=32, M=16, T=12, sigma_eps=(0.0, 0.0), gamma=0.0, **kw)
+        ctl = R.Controller(p, obs, debug=True, allow_zero_noise=True)
+        g = gpu_step(ctl, x0, V0, 3)
+        o = oracle.step(p, obs, x0, V0, 3)
+        ok = (o["obs_margin"] >= 1e-3) & (o["obs_cond"] >= 0.25)
+        assert np.all(rel_err(g["L"], o["L"])[ok] <= 1e-4)
+        ctl.close()
