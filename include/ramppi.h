@@ -182,6 +182,56 @@ mppi_status mppi_normals(uint64_t seed, const uint32_t *ctr_dev, float *out_dev,
 mppi_status mppi_cvar(const float *L_dev, int32_t K, int32_t M, float alpha, float B,
                       float *cvar_dev, void *stream);
 
+/* ---- Batched serving: many independent controllers per launch ---- */
+
+typedef struct mppi_batch mppi_batch;
+
+/* Workspace bytes for a batch of n controllers with parameters p[0..n-1]
+ * (each valid for mppi_create, with M <= 256); 0 when any is rejected.  No
+ * device call. */
+size_t mppi_batch_workspace_bytes(int32_t n, const mppi_params *p);
+
+/* Creates a batch of n independent controllers (Algorithm 1 for each), served
+ * by one step call.  p[i] and obstacles_host[i] (n_obs_i x 3, copied) are as
+ * for mppi_create; V_dev[i] is controller i's caller-owned T_i x 2 mean
+ * sequence, updated in place by every step and fixed for the batch's life;
+ * workspace_dev holds mppi_batch_workspace_bytes(n, p) bytes, 256-byte
+ * aligned.  The library owns the handle, a private capture stream and two
+ * small mapped pinned host buffers (inputs and first commands).
+ * Synchronises `stream`. */
+mppi_status mppi_batch_create(int32_t n, const mppi_params *p, const float *const *obstacles_host,
+                              float *const *V_dev, void *workspace_dev, size_t workspace_bytes,
+                              void *stream, mppi_batch **out);
+
+/* One step of every controller: x0_host n x 4 measured states (finite),
+ * step_idx_host n call indices, u0_host NULL or n x 2 (first commands before
+ * any shift; the call then waits for the step).  The step is three kernels:
+ * per-controller set-up, one persistent rollout launch whose workgroups take
+ * (controller, workgroup) items from a queue, and one update launch over every
+ * controller's chunks; with the graph on (the default) they are replayed from
+ * a HIP graph captured on the first step.  Controller i's results equal those
+ * of mppi_step with the same parameters and inputs.  Before writing the inputs
+ * the call waits for the previous step of this batch. */
+mppi_status mppi_batch_step(mppi_batch *b, const float *x0_host, const uint32_t *step_idx_host,
+                            float *u0_host, void *stream);
+
+/* Picks the persistent grid (workgroups per compute unit, powers of two up to
+ * the occupancy limit) and the queue order (0: controller order, 1: longest
+ * workgroups first) by timing `trials` steps of each candidate with the last
+ * inputs; the mean sequences are restored afterwards.  Writes the choice to
+ * the non-NULL outputs. */
+mppi_status mppi_batch_autotune(mppi_batch *b, int32_t trials, void *stream, int32_t *wg_per_cu,
+                                int32_t *order);
+
+/* enable != 0: replay the step from a HIP graph (the default); 0: launch. */
+mppi_status mppi_batch_set_graph(mppi_batch *b, int enable);
+
+/* Device pointers of controller i's intermediate results (see mppi_debug_ptrs). */
+mppi_status mppi_batch_debug_view(const mppi_batch *b, int32_t i, mppi_debug_ptrs *out);
+
+/* Waits for the batch's last step and destroys the handle (NULL is accepted). */
+mppi_status mppi_batch_destroy(mppi_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -115,6 +115,10 @@ def _load():
         lib.orc_disturbed_cost.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_int, ctypes.c_int,
                                            ctypes.c_uint32, P(D), P(D)]
         lib.orc_disturbed_cost.restype = D
+        lib.orc_running_cost_grad.argtypes = [P(_Params), P(D), P(D)]
+        lib.orc_terminal_cost_grad.argtypes = [P(_Params), P(D), P(D)]
+        lib.orc_free_energy.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_uint32, P(D)]
+        lib.orc_free_energy.restype = D
         lib.orc_set_threads.argtypes = [ctypes.c_int]
         lib.orc_get_threads.restype = ctypes.c_int
         lib.orc_step.argtypes = [P(_Params), P(D), P(D), P(D), ctypes.c_uint32] + [P(D)] * 12
@@ -423,3 +427,35 @@ def rollout_subset(p: dict, obs, x0, V, step_idx: int, k0: int, nk: int) -> tupl
     _load().orc_rollout_subset(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(Va), int(step_idx) & 0xFFFFFFFF,
                                int(k0), int(nk), _dptr(S), _dptr(L))
     return S, L
+
+
+# ------------------------------------------------------------- gradient ----
+
+def running_cost_grad(p: dict, x) -> np.ndarray:
+    s = make_params(p, 0)
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    g = np.zeros(4)
+    _load().orc_running_cost_grad(ctypes.byref(s), _dptr(xa), _dptr(g))
+    return g
+
+
+def terminal_cost_grad(p: dict, x) -> np.ndarray:
+    s = make_params(p, 0)
+    xa = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    g = np.zeros(4)
+    _load().orc_terminal_cost_grad(ctypes.byref(s), _dptr(xa), _dptr(g))
+    return g
+
+
+def free_energy(p: dict, obs, x0, V, step_idx: int, grad: bool = False):
+    """J(V) = -lambda log mean_k exp(-S~_k/lambda) with the noise fixed, and
+    optionally dJ/dV (T x 2).  V is taken as float64 as given (not rounded),
+    so that finite differences can perturb it."""
+    o = _as_f64(obs).reshape(-1, 3)
+    s = make_params(p, o.shape[0])
+    a0 = _as_f64(x0)
+    Va = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1))
+    g = np.zeros(Va.size) if grad else None
+    J = _load().orc_free_energy(ctypes.byref(s), _dptr(o), _dptr(a0), _dptr(Va), int(step_idx) & 0xFFFFFFFF,
+                                _dptr(g) if grad else None)
+    return (J, g.reshape(-1, 2)) if grad else J

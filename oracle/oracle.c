@@ -630,3 +630,227 @@ int orc_rollout_subset(const orc_params *p, const double *obs, const double x0[4
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of the free energy with respect to the mean sequence V.          */
+/*                                                                            */
+/* J(V) = -lambda log((1/K) sum_k exp(-S~_k(V)/lambda)) with the noise held    */
+/* fixed; dJ/dV = sum_k w_hat_k dS~_k/dV (the weights of Eq. 17).  With       */
+/* Eq. 14-16 and 18-19: dS~_k = dS_k + A 1[CVaR_k > C_u] dCVaR_k, and         */
+/* dCVaR_k = (1/n_tail) sum over the tail of dL_a = B dL_m + (1 - B) dLbar.   */
+/* Indicators (collisions, the C_u test, tail membership) have zero gradient  */
+/* almost everywhere.  u = clamp(v + eps) has du/dv = 1 strictly inside the   */
+/* box for warm samples and 0 otherwise.  Rollouts are differentiated by the  */
+/* backward (adjoint) recursion of the Euler steps.                           */
+/* ------------------------------------------------------------------------ */
+
+/* Gradient of the running cost q with respect to the state (Eq. 20-21; the
+ * obstacle indicator of Eq. 22 contributes nothing). */
+void orc_running_cost_grad(const orc_params *p, const double x[4], double g[4])
+{
+    const double pi = 3.141592653589793238462643383279;
+    double a = p->track[2], b = p->track[3];
+    double X = x[0] - p->track[0], Y = x[1] - p->track[1];
+    double G = (X / a) * (X / a) + (Y / b) * (Y / b) - 1.0;
+    double gx = 2.0 * X / (a * a), gy = 2.0 * Y / (b * b);
+    double gn = sqrt(gx * gx + gy * gy);
+    double deX = 0.0, deY = 0.0, e;
+    if (gn < 1e-12) {
+        e = G / 1e-12;
+        deX = gx / 1e-12;
+        deY = gy / 1e-12;
+    } else {
+        e = G / gn;
+        deX = gx / gn - G * gx * (2.0 / (a * a)) / (gn * gn * gn);
+        deY = gy / gn - G * gy * (2.0 / (b * b)) / (gn * gn * gn);
+    }
+    g[0] = 2.0 * p->c_dev * e * deX;
+    g[1] = 2.0 * p->c_dev * e * deY;
+    g[2] = 0.0;
+    g[3] = 2.0 * p->c_v * (x[3] - p->v_ref);
+    if (p->c_bdry != 0.0) {
+        double d = p->track[4] - fabs(e);
+        double dmu_dd = -100.0 / (pi * (1.0 + 1e4 * d * d));
+        double sgn = (e > 0.0) - (e < 0.0);
+        g[0] += p->c_bdry * dmu_dd * (-sgn) * deX;
+        g[1] += p->c_bdry * dmu_dd * (-sgn) * deY;
+    }
+}
+
+/* Gradient of the terminal cost (Eq. 23) with respect to x_T. */
+void orc_terminal_cost_grad(const orc_params *p, const double x[4], double g[4])
+{
+    double a = p->track[2], b = p->track[3];
+    double xi = (x[0] - p->track[0]) / a, et = (x[1] - p->track[1]) / b;
+    double r2 = xi * xi + et * et;
+    double k = -p->c5 * 0.5 * (a + b);
+    g[0] = (r2 > 0.0) ? k * (-et / (a * r2)) : 0.0;
+    g[1] = (r2 > 0.0) ? k * (xi / (b * r2)) : 0.0;
+    g[2] = 0.0;
+    g[3] = 0.0;
+}
+
+/* Backward recursion through one rollout given its states xs[0..T] and
+ * controls uk: gu[t] = dCost/du_t, where Cost = sum_{t<T} q(x_t) [+ phi(x_T)]. */
+static void orc_rollout_adjoint(const orc_params *p, const double *xs, const double *uk, int terminal,
+                                double *gu)
+{
+    int T = p->T;
+    double lam[4] = { 0.0, 0.0, 0.0, 0.0 };
+    if (terminal && (p->c4 != 0.0 || p->c5 != 0.0)) orc_terminal_cost_grad(p, xs + 4 * T, lam);
+    for (int t = T - 1; t >= 0; --t) {
+        const double *x = xs + 4 * t;
+        double psi = x[2], v = x[3], delta = uk[2 * t + 1];
+        double c = cos(psi), s = sin(psi), tn = tan(delta), sec2 = 1.0 + tn * tn;
+        double dt = p->dt, L = p->wheelbase;
+        /* controls: d(psi')/d(delta) = dt v sec^2(delta)/L, d(v')/d(a) = dt */
+        gu[2 * t + 0] = dt * lam[3];
+        gu[2 * t + 1] = dt * v * sec2 / L * lam[2];
+        double gq[4];
+        orc_running_cost_grad(p, x, gq);
+        double nl[4];
+        nl[0] = gq[0] + lam[0];
+        nl[1] = gq[1] + lam[1];
+        nl[2] = gq[2] + lam[0] * (-dt * v * s) + lam[1] * (dt * v * c) + lam[2];
+        nl[3] = gq[3] + lam[0] * (dt * c) + lam[1] * (dt * s) + lam[2] * (dt * tn / L) + lam[3];
+        lam[0] = nl[0]; lam[1] = nl[1]; lam[2] = nl[2]; lam[3] = nl[3];
+    }
+}
+
+/* States of the nominal (m < 0) or disturbed (draw m) rollout of sample k. */
+static void orc_rollout_states(const orc_params *p, const double x0[4], const double *uk, int k, int m,
+                               uint32_t step_idx, double *xs)
+{
+    for (int i = 0; i < 4; ++i) xs[i] = x0[i];
+    for (int t = 0; t < p->T; ++t) {
+        double xn[4];
+        orc_dynamics(xs + 4 * t, uk + 2 * t, p->dt, p->wheelbase, xn);
+        if (m >= 0) {
+            uint32_t ctr[4] = { (uint32_t)t, (uint32_t)m, (uint32_t)k, step_idx };
+            double w[4];
+            orc_disturbance(p, ctr, w);
+            for (int i = 0; i < 4; ++i) xn[i] += w[i];
+        }
+        for (int i = 0; i < 4; ++i) xs[4 * (t + 1) + i] = xn[i];
+    }
+}
+
+/* du/dv of sample k at step t (per component). */
+static void orc_control_jacobian(const orc_params *p, const double *V, uint32_t step_idx, int n_warm, int k, int t,
+                                 double dudv[2])
+{
+    if (k >= n_warm) { dudv[0] = dudv[1] = 0.0; return; }
+    uint32_t ctr[4] = { (uint32_t)t, ORC_CTRL_WORD, (uint32_t)k, step_idx };
+    double z[4];
+    orc_normals4(ctr, p->seed, z);
+    double raw0 = V[2 * t] + sqrt(p->sigma_eps[0]) * z[0];
+    double raw1 = V[2 * t + 1] + sqrt(p->sigma_eps[1]) * z[1];
+    dudv[0] = (raw0 > p->u_lo[0] && raw0 < p->u_hi[0]) ? 1.0 : 0.0;
+    dudv[1] = (raw1 > p->u_lo[1] && raw1 < p->u_hi[1]) ? 1.0 : 0.0;
+}
+
+/* dS~_k/dV (T x 2) of one sample; also returns S~_k. */
+static double orc_sample_grad(const orc_params *p, const double *obs, const double x0[4], const double *V,
+                              uint32_t step_idx, int n_warm, int k, double *gS, double *xs, double *gu,
+                              double *L, double *La, int *idx)
+{
+    int T = p->T, M = p->M;
+    double *uk = (double *)malloc(sizeof(double) * 2 * (size_t)T);
+    double *dudv = (double *)malloc(sizeof(double) * 2 * (size_t)T);
+    for (int t = 0; t < T; ++t) {
+        orc_sample_control(p, V, step_idx, n_warm, k, t, uk + 2 * t);
+        orc_control_jacobian(p, V, step_idx, n_warm, k, t, dudv + 2 * t);
+    }
+    /* nominal: running + control + terminal cost */
+    double S = orc_nominal_cost(p, obs, x0, V, uk, NULL, NULL);
+    orc_rollout_states(p, x0, uk, k, -1, step_idx, xs);
+    orc_rollout_adjoint(p, xs, uk, 1, gu);
+    for (int t = 0; t < T; ++t) {
+        for (int c = 0; c < 2; ++c) {
+            double g = gu[2 * t + c] * dudv[2 * t + c];
+            if (p->gamma != 0.0)
+                g += p->gamma / p->sigma_eps[c] * (uk[2 * t + c] + V[2 * t + c] * dudv[2 * t + c]);
+            gS[2 * t + c] = g;
+        }
+    }
+    /* risk: CVaR of the scaled draws */
+    for (int m = 0; m < M; ++m) L[m] = orc_disturbed_cost(p, obs, x0, uk, k, m, step_idx, NULL, NULL);
+    orc_scale_risk(L, M, p->B, La);
+    int k_alpha, n_tail;
+    orc_tail_size(p->alpha, M, &k_alpha, &n_tail);
+    /* tail = the n_tail largest scaled costs (indices sorted by value, descending) */
+    for (int m = 0; m < M; ++m) idx[m] = m;
+    for (int i = 1; i < M; ++i) {          /* insertion sort, stable, descending */
+        int v = idx[i], j = i - 1;
+        while (j >= 0 && La[idx[j]] < La[v]) { idx[j + 1] = idx[j]; --j; }
+        idx[j + 1] = v;
+    }
+    double cv = 0.0;
+    for (int i = 0; i < n_tail; ++i) cv += La[idx[i]];
+    cv /= (double)n_tail;
+    double St = orc_filtered_cost(S, cv, p->A, p->C_u);
+    if (cv > p->C_u && p->A != 0.0) {
+        /* dCVaR = (1/n_tail) sum_tail [B dL_m + (1 - B) dLbar] */
+        double *dsum = (double *)calloc(2 * (size_t)T, sizeof(double));
+        double *dmean = (double *)calloc(2 * (size_t)T, sizeof(double));
+        char *in_tail = (char *)calloc((size_t)M, 1);
+        for (int i = 0; i < n_tail; ++i) in_tail[idx[i]] = 1;
+        for (int m = 0; m < M; ++m) {
+            if (!in_tail[m] && p->B == 1.0) continue;
+            orc_rollout_states(p, x0, uk, k, m, step_idx, xs);
+            orc_rollout_adjoint(p, xs, uk, 0, gu);
+            for (int j = 0; j < 2 * T; ++j) {
+                double g = gu[j] * dudv[j];
+                if (in_tail[m]) dsum[j] += g;
+                dmean[j] += g / (double)M;
+            }
+        }
+        for (int j = 0; j < 2 * T; ++j) {
+            double d = (p->B == 1.0) ? dsum[j] / n_tail
+                                     : (p->B * dsum[j] + (1.0 - p->B) * n_tail * dmean[j]) / n_tail;
+            gS[j] += p->A * d;
+        }
+        free(dsum); free(dmean); free(in_tail);
+    }
+    free(uk); free(dudv);
+    return St;
+}
+
+/* Free energy J and its gradient dJ/dV (T x 2; may be NULL). */
+double orc_free_energy(const orc_params *p, const double *obs, const double x0[4], const double *V,
+                       uint32_t step_idx, double *grad)
+{
+    int K = p->K, T = p->T, M = p->M;
+    int n_warm = orc_n_warm(p->eta, K);
+    double *St = (double *)malloc(sizeof(double) * (size_t)K);
+    double *G = grad ? (double *)malloc(sizeof(double) * (size_t)K * 2 * T) : NULL;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads)
+#endif
+    for (int k = 0; k < K; ++k) {
+        double *xs = (double *)malloc(sizeof(double) * 4 * (size_t)(T + 1));
+        double *gu = (double *)malloc(sizeof(double) * 2 * (size_t)T);
+        double *L = (double *)malloc(sizeof(double) * (size_t)M);
+        double *La = (double *)malloc(sizeof(double) * (size_t)M);
+        int *idx = (int *)malloc(sizeof(int) * (size_t)M);
+        double *gS = G ? G + (size_t)k * 2 * T : (double *)malloc(sizeof(double) * 2 * (size_t)T);
+        St[k] = orc_sample_grad(p, obs, x0, V, step_idx, n_warm, k, gS, xs, gu, L, La, idx);
+        if (!G) free(gS);
+        free(xs); free(gu); free(L); free(La); free(idx);
+    }
+    double beta = INFINITY;
+    for (int k = 0; k < K; ++k) if (St[k] < beta) beta = St[k];
+    double Z = 0.0;
+    for (int k = 0; k < K; ++k) Z += exp(-(St[k] - beta) / p->lambda);
+    double J = beta - p->lambda * log(Z / (double)K);
+    if (grad) {
+        for (int j = 0; j < 2 * T; ++j) grad[j] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double wh = exp(-(St[k] - beta) / p->lambda) / Z;
+            for (int j = 0; j < 2 * T; ++j) grad[j] += wh * G[(size_t)k * 2 * T + j];
+        }
+        free(G);
+    }
+    free(St);
+    return J;
+}

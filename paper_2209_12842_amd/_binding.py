@@ -88,6 +88,20 @@ def lib():
         L.mppi_normals.restype = ctypes.c_int
         L.mppi_cvar.argtypes = [V, I32, I32, F, F, V, V]
         L.mppi_cvar.restype = ctypes.c_int
+        L.mppi_batch_workspace_bytes.argtypes = [I32, P(Params)]
+        L.mppi_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.mppi_batch_create.argtypes = [I32, P(Params), P(P(F)), P(V), V, ctypes.c_size_t, V, P(V)]
+        L.mppi_batch_create.restype = ctypes.c_int
+        L.mppi_batch_step.argtypes = [V, P(F), P(U32), P(F), V]
+        L.mppi_batch_step.restype = ctypes.c_int
+        L.mppi_batch_autotune.argtypes = [V, I32, V, P(I32), P(I32)]
+        L.mppi_batch_autotune.restype = ctypes.c_int
+        L.mppi_batch_set_graph.argtypes = [V, ctypes.c_int]
+        L.mppi_batch_set_graph.restype = ctypes.c_int
+        L.mppi_batch_debug_view.argtypes = [V, I32, P(DebugPtrs)]
+        L.mppi_batch_debug_view.restype = ctypes.c_int
+        L.mppi_batch_destroy.argtypes = [V]
+        L.mppi_batch_destroy.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -270,3 +284,92 @@ def cvar(L, alpha: float, B: float = 1.0):
     check(lib().mppi_cvar(ctypes.c_void_p(L.data_ptr()), L.shape[0], L.shape[1], float(alpha), float(B),
                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_ptr(L.device))))
     return out
+
+
+class Batch:
+    """Many independent controllers served by one step call (mppi_batch_*).
+
+    params: list of workload dicts, obstacles: list of n_i x 3 arrays.  Each
+    controller's mean sequence is a T_i x 2 float32 tensor in `self.V[i]`,
+    updated in place by every step."""
+
+    def __init__(self, params: list, obstacles: list, device="cuda", debug: bool = False, V0=None):
+        torch = _torch()
+        L = lib()
+        n = len(params)
+        self.n = n
+        obs = [np.ascontiguousarray(np.asarray(o, dtype=np.float32).reshape(-1, 3)) for o in obstacles]
+        flags = MPPI_F_DEBUG if debug else 0
+        self.p = (Params * n)(*[make_params(params[i], obs[i].shape[0], flags) for i in range(n)])
+        nbytes = L.mppi_batch_workspace_bytes(n, self.p)
+        if nbytes == 0:
+            raise MppiError(MPPI_EINVAL, last_error())
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.V = []
+        for i in range(n):
+            T = self.p[i].T
+            v = torch.zeros((T, 2), dtype=torch.float32, device=self.device)
+            if V0 is not None and V0[i] is not None:
+                v.copy_(torch.as_tensor(np.asarray(V0[i], dtype=np.float32).reshape(T, 2)))
+            self.V.append(v)
+        self._obs = obs
+        optrs = (ctypes.POINTER(ctypes.c_float) * n)(*[o.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) for o in obs])
+        vptrs = (ctypes.c_void_p * n)(*[v.data_ptr() for v in self.V])
+        self._h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(L.mppi_batch_create(n, self.p, optrs, vptrs, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                      ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(self._h)))
+        self._x0 = (ctypes.c_float * (4 * n))()
+        self._idx = (ctypes.c_uint32 * n)()
+        self._u0 = (ctypes.c_float * (2 * n))()
+
+    def step(self, x0, step_idx, want_u0: bool = True):
+        """x0: n x 4 states; step_idx: an int (same for all) or n ints."""
+        torch = _torch()
+        xs = np.asarray(x0, dtype=np.float32).reshape(self.n * 4)
+        ctypes.memmove(self._x0, xs.ctypes.data, 16 * self.n)
+        idx = np.broadcast_to(np.asarray(step_idx, dtype=np.uint32), (self.n,))
+        ctypes.memmove(self._idx, np.ascontiguousarray(idx).ctypes.data, 4 * self.n)
+        check(lib().mppi_batch_step(self._h, self._x0, self._idx, self._u0 if want_u0 else None,
+                                    torch.cuda.current_stream(self.device).cuda_stream))
+        if want_u0:
+            return np.frombuffer(self._u0, dtype=np.float32).reshape(self.n, 2).copy()
+        return None
+
+    def autotune(self, trials: int = 3) -> tuple[int, int]:
+        wg, order = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mppi_batch_autotune(self._h, int(trials), ctypes.c_void_p(_stream_ptr(self.device)),
+                                        ctypes.byref(wg), ctypes.byref(order)))
+        return wg.value, order.value
+
+    def set_graph(self, on: bool) -> None:
+        check(lib().mppi_batch_set_graph(self._h, 1 if on else 0))
+
+    def debug(self, i: int) -> dict:
+        torch = _torch()
+        d = DebugPtrs()
+        check(lib().mppi_batch_debug_view(self._h, int(i), ctypes.byref(d)))
+        base = self.workspace.data_ptr()
+        K, T, M = self.p[i].K, self.p[i].T, self.p[i].M
+
+        def view(ptr, shape):
+            n = int(np.prod(shape))
+            off = ptr - base
+            return self.workspace[off:off + 4 * n].view(torch.float32).view(*shape)
+
+        return dict(u=view(d.u, (T, K, 2)), S=view(d.S, (K,)), L=view(d.L, (K, M)), cvar=view(d.cvar, (K,)),
+                    S_tilde=view(d.S_tilde, (K,)), w_hat=view(d.w_hat, (K,)), u0=view(d.u0, (2,)))
+
+    def close(self) -> None:
+        if self._h:
+            lib().mppi_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

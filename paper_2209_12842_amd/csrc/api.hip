@@ -5,8 +5,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "launch.h"
@@ -101,6 +103,85 @@ mppi_status check_device(int* dev) {
     e = hipGetDevice(dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     return MPPI_OK;
+}
+
+// Per-launch constants that depend only on the parameters and the geometry.
+void fill_static(ramppi::StepConst* cp, const mppi_params& p, const Geometry& g, int n_tail, int n_warm) {
+    ramppi::StepConst& c = *cp;
+    std::memset(&c, 0, sizeof c);
+    c.K = p.K;
+    c.T = p.T;
+    c.M = p.M;
+    c.n_obs = p.n_obs;
+    c.spb = g.spb;
+    c.n_nom_wg = g.n_nom_wg;
+    c.n_warm = n_warm;
+    c.n_tail = n_tail;
+    c.dt = p.dt;
+    c.inv_wheelbase = (float)(1.0 / (double)p.wheelbase);
+    c.u_lo0 = p.u_lo[0];
+    c.u_lo1 = p.u_lo[1];
+    c.u_hi0 = p.u_hi[0];
+    c.u_hi1 = p.u_hi[1];
+    c.se0 = (float)std::sqrt((double)p.sigma_eps[0]);
+    c.se1 = (float)std::sqrt((double)p.sigma_eps[1]);
+    c.sw0 = (float)std::sqrt((double)p.sigma_w[0]);
+    c.sw1 = (float)std::sqrt((double)p.sigma_w[1]);
+    c.sw2 = (float)std::sqrt((double)p.sigma_w[2]);
+    c.sw3 = (float)std::sqrt((double)p.sigma_w[3]);
+    c.noise_kind = (int32_t)p.noise_kind;
+    if (p.noise_kind == MPPI_NOISE_UNIFORM) {  // half widths sqrt(3 sigma_w) in the sw slots
+        c.sw0 = (float)std::sqrt(3.0 * p.sigma_w[0]);
+        c.sw1 = (float)std::sqrt(3.0 * p.sigma_w[1]);
+        c.sw2 = (float)std::sqrt(3.0 * p.sigma_w[2]);
+        c.sw3 = (float)std::sqrt(3.0 * p.sigma_w[3]);
+    }
+    c.jump_prob = p.jump_prob;
+    c.jump_size = p.jump_size;
+    c.gamma = p.gamma;
+    c.use_ctrl = p.gamma != 0.0f;
+    c.inv_var0 = c.use_ctrl ? (float)(1.0 / (double)p.sigma_eps[0]) : 0.0f;
+    c.inv_var1 = c.use_ctrl ? (float)(1.0 / (double)p.sigma_eps[1]) : 0.0f;
+    c.A = p.A;
+    c.B = p.B;
+    c.C_u = p.C_u;
+    c.lambda = p.lambda;
+    c.scale_risk = p.B != 1.0f;
+    c.c_bdry = p.c_bdry;
+    c.c_obs = p.c_obs;
+    c.c_dev = p.c_dev;
+    c.c_v = p.c_v;
+    c.v_ref = p.v_ref;
+    c.c4 = p.c4;
+    c.c5 = p.c5;
+    c.use_bdry = p.c_bdry != 0.0f;
+    c.use_term = (p.c4 != 0.0f) || (p.c5 != 0.0f);
+    const double a = p.track[2], b = p.track[3];
+    c.inv_a = (float)(1.0 / a);
+    c.inv_b = (float)(1.0 / b);
+    c.g_a = (float)(2.0 / (a * a));
+    c.g_b = (float)(2.0 / (b * b));
+    c.hw = p.track[4];
+    c.half_ab = (float)(0.5 * (a + b));
+    c.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
+    c.key1 = (uint32_t)(p.seed >> 32);
+    c.flags = p.flags;
+    c.debug = (p.flags & MPPI_F_DEBUG) != 0;
+}
+
+// Per-launch constants that depend on the measured state and the call index
+// (the batched path computes the same fields on the device, ramppi::set_dynamic).
+void fill_dynamic(ramppi::StepConst* cp, const mppi_params& p, const float x0[4], uint32_t step_idx) {
+    ramppi::StepConst& c = *cp;
+    c.fx = x0[0];
+    c.fy = x0[1];
+    c.tox = x0[0] - p.track[0];
+    c.toy = x0[1] - p.track[1];
+    c.theta0 = (float)std::atan2(((double)x0[1] - p.track[1]) / (double)p.track[3],
+                                 ((double)x0[0] - p.track[0]) / (double)p.track[2]);
+    c.psi0 = x0[2];
+    c.v0 = x0[3];
+    c.step_idx = step_idx;
 }
 
 }  // namespace
@@ -266,73 +347,8 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     ramppi::StepConst c;
-    std::memset(&c, 0, sizeof c);
-    c.K = p.K;
-    c.T = p.T;
-    c.M = p.M;
-    c.n_obs = p.n_obs;
-    c.spb = g.spb;
-    c.n_nom_wg = g.n_nom_wg;
-    c.n_warm = h->n_warm;
-    c.n_tail = h->n_tail;
-    c.dt = p.dt;
-    c.inv_wheelbase = (float)(1.0 / (double)p.wheelbase);
-    c.u_lo0 = p.u_lo[0];
-    c.u_lo1 = p.u_lo[1];
-    c.u_hi0 = p.u_hi[0];
-    c.u_hi1 = p.u_hi[1];
-    c.se0 = (float)std::sqrt((double)p.sigma_eps[0]);
-    c.se1 = (float)std::sqrt((double)p.sigma_eps[1]);
-    c.sw0 = (float)std::sqrt((double)p.sigma_w[0]);
-    c.sw1 = (float)std::sqrt((double)p.sigma_w[1]);
-    c.sw2 = (float)std::sqrt((double)p.sigma_w[2]);
-    c.sw3 = (float)std::sqrt((double)p.sigma_w[3]);
-    c.noise_kind = (int32_t)p.noise_kind;
-    if (p.noise_kind == MPPI_NOISE_UNIFORM) {  // half widths sqrt(3 sigma_w) in the sw slots
-        c.sw0 = (float)std::sqrt(3.0 * p.sigma_w[0]);
-        c.sw1 = (float)std::sqrt(3.0 * p.sigma_w[1]);
-        c.sw2 = (float)std::sqrt(3.0 * p.sigma_w[2]);
-        c.sw3 = (float)std::sqrt(3.0 * p.sigma_w[3]);
-    }
-    c.jump_prob = p.jump_prob;
-    c.jump_size = p.jump_size;
-    c.gamma = p.gamma;
-    c.use_ctrl = p.gamma != 0.0f;
-    c.inv_var0 = c.use_ctrl ? (float)(1.0 / (double)p.sigma_eps[0]) : 0.0f;
-    c.inv_var1 = c.use_ctrl ? (float)(1.0 / (double)p.sigma_eps[1]) : 0.0f;
-    c.A = p.A;
-    c.B = p.B;
-    c.C_u = p.C_u;
-    c.lambda = p.lambda;
-    c.scale_risk = p.B != 1.0f;
-    c.c_bdry = p.c_bdry;
-    c.c_obs = p.c_obs;
-    c.c_dev = p.c_dev;
-    c.c_v = p.c_v;
-    c.v_ref = p.v_ref;
-    c.c4 = p.c4;
-    c.c5 = p.c5;
-    c.use_bdry = p.c_bdry != 0.0f;
-    c.use_term = (p.c4 != 0.0f) || (p.c5 != 0.0f);
-    c.fx = x0[0];
-    c.fy = x0[1];
-    c.tox = x0[0] - p.track[0];
-    c.toy = x0[1] - p.track[1];
-    const double a = p.track[2], b = p.track[3];
-    c.inv_a = (float)(1.0 / a);
-    c.inv_b = (float)(1.0 / b);
-    c.g_a = (float)(2.0 / (a * a));
-    c.g_b = (float)(2.0 / (b * b));
-    c.hw = p.track[4];
-    c.half_ab = (float)(0.5 * (a + b));
-    c.theta0 = (float)std::atan2(((double)x0[1] - p.track[1]) / b, ((double)x0[0] - p.track[0]) / a);
-    c.psi0 = x0[2];
-    c.v0 = x0[3];
-    c.key0 = (uint32_t)(p.seed & 0xFFFFFFFFu);
-    c.key1 = (uint32_t)(p.seed >> 32);
-    c.step_idx = step_idx;
-    c.flags = p.flags;
-    c.debug = (p.flags & MPPI_F_DEBUG) != 0;
+    fill_static(&c, p, g, h->n_tail, h->n_warm);
+    fill_dynamic(&c, p, x0, step_idx);
 
     ramppi::StepBuffers bufs;
     bufs.obs = reinterpret_cast<const float4*>(h->ws + h->l.obs);
@@ -471,4 +487,421 @@ mppi_status mppi_cvar(const float* L_dev, int32_t K, int32_t M, float alpha, flo
     return e == hipSuccess ? MPPI_OK : hip_fail(e, "cvar launch");
 }
 
+
+// ======================================================================
+// Batched serving (many independent controllers per launch)
+// ======================================================================
 }  // extern "C"
+
+namespace {
+
+constexpr int kBatchBlock = 256;
+constexpr int kMaxBatch = 65535;
+
+// Rollout geometry of a controller inside a batch: workgroups of 256 lanes.
+Geometry batch_geometry(const mppi_params* p) {
+    Geometry g = geometry(p);
+    g.spb = p->M >= kBatchBlock ? 1 : kBatchBlock / p->M;
+    g.block = kBatchBlock;
+    g.n_nom_wg = (p->K + kBatchBlock - 1) / kBatchBlock;
+    g.lds_rollout = 8 * (size_t)g.spb * p->T + 4 * (2 * (size_t)g.spb * p->M + g.spb);
+    return g;
+}
+
+int n_dist_wg(const mppi_params* p, const Geometry& g) { return (p->K + g.spb - 1) / g.spb; }
+
+struct BatchLayout {
+    size_t ctls, items, uitems, queue, vbackup;
+    std::vector<size_t> ctl_base;
+    size_t total;
+    int n_items, n_uitems;
+    size_t lds_rollout, lds_update;
+};
+
+mppi_status batch_check(int32_t n, const mppi_params* p) {
+    if (n < 1 || n > kMaxBatch) return fail(MPPI_EINVAL, "batch size must lie in [1, %d]", kMaxBatch);
+    if (!p) return fail(MPPI_EINVAL, "params is NULL");
+    for (int i = 0; i < n; ++i) {
+        mppi_status st = mppi_validate(&p[i]);
+        if (st != MPPI_OK) {
+            std::string m = g_err;
+            return fail(st, "controller %d: %s", i, m.c_str());
+        }
+        if (p[i].M > kBatchBlock)
+            return fail(MPPI_EUNSUPPORTED, "controller %d: M = %d exceeds %d in a batch", i, p[i].M, kBatchBlock);
+        const Geometry g = batch_geometry(&p[i]);
+        if (g.lds_rollout > kMaxLdsBytes)
+            return fail(MPPI_EUNSUPPORTED, "controller %d: rollout LDS need %zu B exceeds %zu B", i, g.lds_rollout,
+                        kMaxLdsBytes);
+    }
+    return MPPI_OK;
+}
+
+BatchLayout batch_layout(int32_t n, const mppi_params* p) {
+    BatchLayout bl;
+    bl.n_items = 0;
+    bl.n_uitems = 0;
+    bl.lds_rollout = 0;
+    bl.lds_update = 0;
+    size_t vback = 0;
+    for (int i = 0; i < n; ++i) {
+        const Geometry g = batch_geometry(&p[i]);
+        bl.n_items += g.n_nom_wg + n_dist_wg(&p[i], g);
+        bl.n_uitems += g.G;
+        bl.lds_rollout = std::max(bl.lds_rollout, g.lds_rollout);
+        bl.lds_update = std::max(bl.lds_update, g.lds_update);
+        vback += align_up(8 * (size_t)p[i].T);
+    }
+    size_t o = 0;
+    bl.ctls = o;    o += align_up(sizeof(ramppi::BatchCtl) * (size_t)n);
+    bl.items = o;   o += align_up(8 * (size_t)bl.n_items);
+    bl.uitems = o;  o += align_up(8 * (size_t)bl.n_uitems);
+    bl.queue = o;   o += align_up(8);
+    bl.vbackup = o; o += vback;
+    bl.ctl_base.resize(n);
+    for (int i = 0; i < n; ++i) {
+        bl.ctl_base[i] = o;
+        o += layout(&p[i]).total;
+    }
+    bl.total = o;
+    return bl;
+}
+
+}  // namespace
+
+struct mppi_batch {
+    int n, device, num_cu, wg_per_cu, wg_max, order;
+    std::vector<mppi_params> p;
+    std::vector<ramppi::BatchCtl> ctl;  // host copy (device pointers inside)
+    std::vector<float*> V;
+    BatchLayout bl;
+    char* ws;
+    ramppi::BatchInput* in_host;
+    ramppi::BatchInput* in_dev;
+    float* out_host;
+    float* out_dev;
+    std::vector<int2> items[2];  // 0: controller order, 1: longest first
+    bool use_graph, captured, pending;
+    hipStream_t cap;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    hipEvent_t done;
+};
+
+namespace {
+
+ramppi::BatchLaunch batch_launch_args(const mppi_batch* b) {
+    ramppi::BatchLaunch L;
+    L.ctls = reinterpret_cast<ramppi::BatchCtl*>(b->ws + b->bl.ctls);
+    L.inputs = b->in_dev;
+    L.items = reinterpret_cast<const int2*>(b->ws + b->bl.items);
+    L.uitems = reinterpret_cast<const int2*>(b->ws + b->bl.uitems);
+    L.queue = reinterpret_cast<unsigned*>(b->ws + b->bl.queue);
+    L.n_ctl = b->n;
+    L.n_items = b->bl.n_items;
+    L.n_uitems = b->bl.n_uitems;
+    L.grid_rollout = b->wg_per_cu * b->num_cu;
+    L.lds_rollout = b->bl.lds_rollout;
+    L.lds_update = b->bl.lds_update;
+    return L;
+}
+
+void batch_release(mppi_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->in_host) (void)hipHostFree(b->in_host);
+    if (b->out_host) (void)hipHostFree(b->out_host);
+    delete b;
+}
+
+void drop_graph(mppi_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->captured = false;
+}
+
+hipError_t upload_items(mppi_batch* b, int order, hipStream_t s) {
+    const std::vector<int2>& it = b->items[order];
+    return hipMemcpyAsync(b->ws + b->bl.items, it.data(), 8 * it.size(), hipMemcpyHostToDevice, s);
+}
+
+hipError_t batch_launch(mppi_batch* b, hipStream_t s, bool graph) {
+    const ramppi::BatchLaunch L = batch_launch_args(b);
+    if (!graph) return ramppi::launch_batch(L, s);
+    if (!b->captured) {
+        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) return e;
+        e = ramppi::launch_batch(L, b->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+        if (e == hipSuccess) e = e2;
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return e;
+        }
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return e;
+        }
+        b->graph = g;
+        b->captured = true;
+    }
+    return hipGraphLaunch(b->exec, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mppi_batch_workspace_bytes(int32_t n, const mppi_params* p) {
+    if (batch_check(n, p) != MPPI_OK) return 0;
+    return batch_layout(n, p).total;
+}
+
+mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* const* obstacles_host,
+                              float* const* V_dev, void* workspace_dev, size_t workspace_bytes, void* stream,
+                              mppi_batch** out) {
+    if (!out) return fail(MPPI_EINVAL, "out is NULL");
+    *out = nullptr;
+    mppi_status st = batch_check(n, p);
+    if (st != MPPI_OK) return st;
+    if (!obstacles_host || !V_dev) return fail(MPPI_EINVAL, "obstacles_host or V_dev is NULL");
+    for (int i = 0; i < n; ++i) {
+        if (!V_dev[i]) return fail(MPPI_EINVAL, "V_dev[%d] is NULL", i);
+        if (p[i].n_obs > 0 && !obstacles_host[i]) return fail(MPPI_EINVAL, "obstacles_host[%d] is NULL", i);
+        for (int j = 0; j < p[i].n_obs; ++j) {
+            const float* o = obstacles_host[i] + 3 * j;
+            if (!(finite(o[0]) && finite(o[1]) && finite(o[2]) && o[2] > 0))
+                return fail(MPPI_EINVAL, "controller %d obstacle %d must have a finite centre and a radius > 0", i,
+                            j);
+        }
+    }
+    const BatchLayout bl = batch_layout(n, p);
+    if (!workspace_dev) return fail(MPPI_EINVAL, "workspace_dev is NULL");
+    if (((uintptr_t)workspace_dev) % kAlign) return fail(MPPI_EINVAL, "workspace_dev must be 256-byte aligned");
+    if (workspace_bytes < bl.total) return fail(MPPI_EINVAL, "workspace has %zu B, needs %zu B", workspace_bytes, bl.total);
+    int dev = 0;
+    st = check_device(&dev);
+    if (st != MPPI_OK) return st;
+
+    mppi_batch* b = new (std::nothrow) mppi_batch();
+    if (!b) return fail(MPPI_ENOMEM, "host allocation failed");
+    b->n = n;
+    b->device = dev;
+    b->p.assign(p, p + n);
+    b->V.assign(V_dev, V_dev + n);
+    b->bl = bl;
+    b->ws = static_cast<char*>(workspace_dev);
+    b->in_host = nullptr;
+    b->out_host = nullptr;
+    b->use_graph = true;
+    b->captured = false;
+    b->pending = false;
+    b->cap = nullptr;
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->done = nullptr;
+    hipError_t e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = ramppi::batch_rollout_occupancy(&b->wg_max, bl.lds_rollout);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->in_host), sizeof(ramppi::BatchInput) * (size_t)n,
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&b->in_dev), b->in_host, 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&b->out_host), 2 * sizeof(float) * (size_t)n,
+                          hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void**>(&b->out_dev), b->out_host, 0);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return hip_fail(e, "batch set-up");
+    }
+    if (b->wg_max < 1) b->wg_max = 1;
+    b->wg_per_cu = b->wg_max;
+    b->order = 1;
+    std::memset(b->in_host, 0, sizeof(ramppi::BatchInput) * (size_t)n);
+
+    // controllers: static constants and buffer addresses; item lists
+    b->ctl.resize(n);
+    std::vector<std::pair<double, int2>> cost_items;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::vector<int2> uitems;
+    for (int i = 0; i < n; ++i) {
+        const Geometry g = batch_geometry(&p[i]);
+        const Layout l = layout(&p[i]);
+        int n_tail, n_warm;
+        derived_counts(&p[i], &n_tail, &n_warm);
+        ramppi::BatchCtl& c = b->ctl[i];
+        std::memset(&c, 0, sizeof c);
+        fill_static(&c.c, p[i], g, n_tail, n_warm);
+        char* base = b->ws + bl.ctl_base[i];
+        c.obs = reinterpret_cast<const float4*>(base + l.obs);
+        c.tab = reinterpret_cast<float4*>(base + l.tab);
+        c.V = V_dev[i];
+        c.u = reinterpret_cast<float2*>(base + l.u);
+        c.S = reinterpret_cast<float*>(base + l.S);
+        c.cvar = reinterpret_cast<float*>(base + l.cvar);
+        c.S_tilde = reinterpret_cast<float*>(base + l.S_tilde);
+        c.w_hat = reinterpret_cast<float*>(base + l.w_hat);
+        c.L = reinterpret_cast<float*>(base + l.L);
+        c.part = reinterpret_cast<float*>(base + l.part);
+        c.counter = reinterpret_cast<unsigned*>(base + l.counter);
+        c.u0 = reinterpret_cast<float*>(base + l.u0);
+        c.u0_host = b->out_dev + 2 * (size_t)i;
+        c.G = g.G;
+        c.parts = ramppi::update_parts(p[i].T);
+        for (int j = 0; j < 4; ++j) c.track[j] = p[i].track[j];
+        // the cost of any workgroup of this controller: T steps of the
+        // per-step work plus three instructions per obstacle
+        const double cost = (double)p[i].T * (40.0 + 3.0 * (double)((p[i].n_obs + 7) / 8 * 8));
+        const int nw = g.n_nom_wg + n_dist_wg(&p[i], g);
+        for (int w = 0; w < nw; ++w) {
+            b->items[0].push_back(make_int2(i, w));
+            cost_items.push_back({cost, make_int2(i, w)});
+        }
+        for (int ch = 0; ch < g.G; ++ch) uitems.push_back(make_int2(i, ch));
+        std::vector<float> staged(4 * (size_t)(p[i].n_obs > 0 ? p[i].n_obs : 1), 0.0f);
+        for (int j = 0; j < p[i].n_obs; ++j)
+            for (int q = 0; q < 3; ++q) staged[4 * j + q] = obstacles_host[i][3 * j + q];
+        if (e == hipSuccess && p[i].n_obs > 0)
+            e = hipMemcpyAsync(base + l.obs, staged.data(), 16 * (size_t)p[i].n_obs, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(base + l.counter, 0, 4, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // staged is a local buffer
+    }
+    std::stable_sort(cost_items.begin(), cost_items.end(),
+                     [](const std::pair<double, int2>& a, const std::pair<double, int2>& c) { return a.first > c.first; });
+    for (auto& ci : cost_items) b->items[1].push_back(ci.second);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + bl.ctls, b->ctl.data(), sizeof(ramppi::BatchCtl) * (size_t)n,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = upload_items(b, b->order, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->ws + bl.uitems, uitems.data(), 8 * uitems.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.queue, 0, 8, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        batch_release(b);
+        return hip_fail(e, "batch upload");
+    }
+    *out = b;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_step(mppi_batch* b, const float* x0_host, const uint32_t* step_idx_host, float* u0_host,
+                            void* stream) {
+    if (!b) return fail(MPPI_EINVAL, "batch is NULL");
+    if (!x0_host || !step_idx_host) return fail(MPPI_EINVAL, "x0_host or step_idx_host is NULL");
+    for (int i = 0; i < 4 * b->n; ++i)
+        if (!finite(x0_host[i])) return fail(MPPI_EINVAL, "x0 of controller %d is not finite", i / 4);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (b->pending) {  // the previous step may still read the inputs
+        e = hipEventSynchronize(b->done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    for (int i = 0; i < b->n; ++i) {
+        for (int j = 0; j < 4; ++j) b->in_host[i].x0[j] = x0_host[4 * i + j];
+        b->in_host[i].step_idx = step_idx_host[i];
+    }
+    e = batch_launch(b, s, b->use_graph);
+    if (e == hipSuccess) e = hipEventRecord(b->done, s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    b->pending = true;
+    if (u0_host) {
+        e = hipEventSynchronize(b->done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        std::memcpy(u0_host, b->out_host, 2 * sizeof(float) * (size_t)b->n);
+    }
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_set_graph(mppi_batch* b, int enable) {
+    if (!b) return fail(MPPI_EINVAL, "batch is NULL");
+    b->use_graph = enable != 0;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_autotune(mppi_batch* b, int32_t trials, void* stream, int32_t* wg_per_cu, int32_t* order) {
+    if (!b) return fail(MPPI_EINVAL, "batch is NULL");
+    if (trials < 1) return fail(MPPI_EINVAL, "trials must be >= 1");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess && b->pending) e = hipEventSynchronize(b->done);
+    // keep the mean sequences: tuning runs real steps, which update them
+    size_t off = b->bl.vbackup;
+    for (int i = 0; e == hipSuccess && i < b->n; ++i) {
+        e = hipMemcpyAsync(b->ws + off, b->V[i], 8 * (size_t)b->p[i].T, hipMemcpyDeviceToDevice, s);
+        off += align_up(8 * (size_t)b->p[i].T);
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    const int saved_wg = b->wg_per_cu, saved_order = b->order;
+    float best = -1.0f;
+    int best_wg = saved_wg, best_order = saved_order;
+    for (int ord = 0; e == hipSuccess && ord < 2; ++ord) {
+        e = upload_items(b, ord, s);
+        for (int wg = 1; e == hipSuccess && wg <= b->wg_max; wg *= 2) {
+            b->wg_per_cu = wg;
+            e = batch_launch(b, s, false);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(t0, s);
+            for (int r = 0; e == hipSuccess && r < trials; ++r) e = batch_launch(b, s, false);
+            if (e == hipSuccess) e = hipEventRecord(t1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(t1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+            if (e == hipSuccess && (best < 0.0f || ms < best)) {
+                best = ms;
+                best_wg = wg;
+                best_order = ord;
+            }
+        }
+    }
+    b->wg_per_cu = best_wg;
+    b->order = best_order;
+    if (e == hipSuccess) e = upload_items(b, best_order, s);
+    off = b->bl.vbackup;
+    for (int i = 0; e == hipSuccess && i < b->n; ++i) {
+        e = hipMemcpyAsync(b->V[i], b->ws + off, 8 * (size_t)b->p[i].T, hipMemcpyDeviceToDevice, s);
+        off += align_up(8 * (size_t)b->p[i].T);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    drop_graph(b);  // the grid changed: capture again on the next step
+    b->pending = false;
+    if (e != hipSuccess) return hip_fail(e, "autotune");
+    if (wg_per_cu) *wg_per_cu = best_wg;
+    if (order) *order = best_order;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_debug_view(const mppi_batch* b, int32_t i, mppi_debug_ptrs* out) {
+    if (!b || !out) return fail(MPPI_EINVAL, "batch or out is NULL");
+    if (i < 0 || i >= b->n) return fail(MPPI_EINVAL, "controller index %d out of range", i);
+    const ramppi::BatchCtl& c = b->ctl[i];
+    out->u = reinterpret_cast<const float*>(c.u);
+    out->S = c.S;
+    out->L = c.L;
+    out->cvar = c.cvar;
+    out->S_tilde = c.S_tilde;
+    out->w_hat = c.w_hat;
+    out->u0 = c.u0;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_destroy(mppi_batch* b) {
+    if (!b) return MPPI_OK;
+    if (b->pending) (void)hipEventSynchronize(b->done);
+    batch_release(b);
+    return MPPI_OK;
+}
+
+}  // extern "C"
+

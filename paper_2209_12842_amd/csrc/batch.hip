@@ -1,0 +1,110 @@
+// Batched serving: one step of many independent controllers (uneven K, T, M
+// and obstacle counts) in three launches that a HIP graph can hold:
+//   k_batch_prep     one workgroup per controller: reads the controller's
+//                    measured state and call index from mapped host memory,
+//                    completes its per-step constants and writes its
+//                    obstacle table in the frame of its start position;
+//   k_batch_rollout  persistent: a fixed grid of workgroups takes
+//                    (controller, workgroup) items from a queue (an atomic
+//                    counter over an item list ordered by the host, by
+//                    default longest first) and runs the same rollout body as
+//                    the single-controller kernel; every workgroup leaves
+//                    when the queue is empty, and the last one to leave
+//                    resets the queue for the next launch;
+//   k_batch_update   one workgroup per (controller, chunk) item, the same
+//                    update body as the single-controller kernel, merged per
+//                    controller by its last chunk.
+// Nothing waits for another workgroup, so every wave reaches its exit.
+#include "launch.h"
+#include "step_device.h"
+
+namespace ramppi {
+
+// Per-step constants that depend on the measured state (the same arithmetic
+// as the host-side fill for a single controller).
+__device__ __forceinline__ void set_dynamic(StepConst& c, const BatchCtl& b, const BatchInput& in) {
+    c.fx = in.x0[0];
+    c.fy = in.x0[1];
+    c.tox = in.x0[0] - b.track[0];
+    c.toy = in.x0[1] - b.track[1];
+    c.theta0 = (float)atan2(((double)in.x0[1] - (double)b.track[1]) / (double)b.track[3],
+                            ((double)in.x0[0] - (double)b.track[0]) / (double)b.track[2]);
+    c.psi0 = in.x0[2];
+    c.v0 = in.x0[3];
+    c.step_idx = in.step_idx;
+}
+
+__global__ void __launch_bounds__(256) k_batch_prep(BatchCtl* __restrict__ ctls,
+                                                    const BatchInput* __restrict__ inputs) {
+    __shared__ float f[2];
+    BatchCtl& b = ctls[blockIdx.x];
+    if (threadIdx.x == 0) {
+        const BatchInput in = inputs[blockIdx.x];
+        set_dynamic(b.c, b, in);
+        f[0] = in.x0[0];
+        f[1] = in.x0[1];
+    }
+    __syncthreads();
+    const int n_obs = b.c.n_obs;
+    const int n_pad = (n_obs + 7) & ~7;
+    for (int i = threadIdx.x; i < n_pad; i += blockDim.x) b.tab[i] = obstacle_entry(b.obs, n_obs, i, f[0], f[1]);
+}
+
+__global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restrict__ ctls,
+                                                       const int2* __restrict__ items, int n_items,
+                                                       unsigned* queue) {
+    extern __shared__ float2 bsmem[];
+    __shared__ int item_sh;
+    for (;;) {
+        if (threadIdx.x == 0) item_sh = (int)atomicAdd(&queue[0], 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(item_sh);
+        __syncthreads();  // every lane has read item_sh before it is overwritten
+        if (it >= n_items) break;
+        const int2 cw = items[it];
+        const BatchCtl& b = ctls[__builtin_amdgcn_readfirstlane(cw.x)];
+        const int w = __builtin_amdgcn_readfirstlane(cw.y);
+        const StepConst c = b.c;
+        const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
+        if (c.noise_kind == 1)
+            rollout_body<1>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem);
+        else if (c.noise_kind == 2)
+            rollout_body<2>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem);
+        else
+            rollout_body<0>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem);
+        __syncthreads();  // LDS is reused by the next item
+    }
+    if (threadIdx.x == 0) {
+        const unsigned done = __hip_atomic_fetch_add(&queue[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == gridDim.x - 1) {  // every other workgroup has left: reset for the next launch
+            __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict__ ctls,
+                                                      const int2* __restrict__ uitems) {
+    extern __shared__ float bush[];
+    __shared__ float red[4];
+    __shared__ int is_last;
+    const int2 cb = uitems[blockIdx.x];
+    const BatchCtl& b = ctls[cb.x];
+    const StepConst c = b.c;
+    update_body(c, cb.y, b.G, b.parts, b.S, b.cvar, b.u, b.S_tilde, b.part, b.counter, b.V, b.u0, b.u0_host,
+                b.w_hat, bush, red, &is_last);
+}
+
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream) {
+    hipLaunchKernelGGL(k_batch_prep, dim3(L.n_ctl), dim3(256), 0, stream, L.ctls, L.inputs);
+    hipLaunchKernelGGL(k_batch_rollout, dim3(L.grid_rollout), dim3(256), L.lds_rollout, stream, L.ctls, L.items,
+                       L.n_items, L.queue);
+    hipLaunchKernelGGL(k_batch_update, dim3(L.n_uitems), dim3(256), L.lds_update, stream, L.ctls, L.uitems);
+    return hipGetLastError();
+}
+
+hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_batch_rollout, 256, lds_rollout);
+}
+
+}  // namespace ramppi

@@ -14,62 +14,18 @@
 //               (Eq. 4), the optional shift and the first command (also
 //               stored straight into mapped host memory when it is wanted).
 // Every reduction runs in a fixed order, so a step is bit-reproducible.
-#include "device.h"
 #include "launch.h"
+#include "step_device.h"
 
 namespace ramppi {
 
 // Obstacle table of one step in the local frame centred on the start
-// position: tab[i] = (-2 cx, -2 cy, r^2 - cx^2 - cy^2, 0) for i < n_obs, and
-// entries up to the next multiple of 8 that no point can hit (tab.z = -inf).
+// position (see obstacle_entry), padded to a multiple of 8 entries.
 __global__ void __launch_bounds__(256) k_obstacle_frame(const float4* __restrict__ obs, int n_obs, float fx,
                                                         float fy, float4* __restrict__ tab) {
     const int n_pad = (n_obs + 7) & ~7;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x) {
-        if (i < n_obs) {
-            const float4 o = obs[i];  // cx, cy, r, unused
-            const float cx = o.x - fx;
-            const float cy = o.y - fy;
-            tab[i] = make_float4(-2.0f * cx, -2.0f * cy, __fmaf_rn(o.z, o.z, -__fmaf_rn(cx, cx, cy * cy)), 0.0f);
-        } else {
-            tab[i] = make_float4(0.0f, 0.0f, -__builtin_inff(), 0.0f);
-        }
-    }
-}
-
-// LDS layout of k_rollout (dynamic shared memory, in this order):
-//   float2 ctl[spb * T]   (dt a, tan(delta) / wheelbase) of the WG's samples
-//   float  vals[spb * M]  risk costs of the WG's samples
-//   float  tail[spb * M]  tail slots (descending)
-//   float  means[spb]     mean risk cost per sample (risk scaling)
-// Scal, Max and Average of Algorithm 1 for the spb samples of a workgroup.
-// vals holds the raw risk costs (thread tid owns slot tid for tid < spb * M);
-// returns the CVaR in the m == 0 lane of each sample.
-__device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* means, int spb, int M,
-                                               int n_tail, int scale_risk, float B) {
-    const int tid = threadIdx.x;
-    const int sl = tid / M;
-    const int m = tid - sl * M;
-    const bool own = sl < spb;
-    __syncthreads();  // vals and tail initialisation visible
-    if (scale_risk) {
-        if (own && m == 0) {
-            float s = 0.0f;
-            for (int j = 0; j < M; ++j) s += vals[sl * M + j];
-            means[sl] = s / (float)M;
-        }
-        __syncthreads();
-        if (own) {
-            const float mu = means[sl];
-            vals[tid] = __fmaf_rn(B, vals[tid] - mu, mu);
-        }
-        __syncthreads();
-    }
-    if (own) tail_rank_scatter(vals + sl * M, tail + sl * M, M, m, n_tail);
-    __syncthreads();
-    float cv = 0.0f;
-    if (own && m == 0) cv = tail_sum(tail + sl * M, n_tail);
-    return cv;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x)
+        tab[i] = obstacle_entry(obs, n_obs, i, fx, fy);
 }
 
 template <int kNoise>
@@ -78,122 +34,9 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
                                                   float* __restrict__ L_out) {
     extern __shared__ float2 smem[];
-    float2* ctl = smem;
-    float* vals = reinterpret_cast<float*>(ctl + (size_t)c.spb * c.T);
-    float* tail = vals + c.spb * c.M;
-    float* means = tail + c.spb * c.M;
-    const int tid = threadIdx.x;
-    const int n_oct = (c.n_obs + 7) >> 3;
-
-    if ((int)blockIdx.x < c.n_nom_wg) {
-        // ---- nominal rollouts: one lane per sample ----
-        const int k = blockIdx.x * blockDim.x + tid;
-        if (k >= c.K) return;
-        State s{0.0f, 0.0f, c.psi0, c.v0};
-        float acc = 0.0f, ctrl = 0.0f;
-        int cnt = 0;
-        for (int t = 0; t < c.T; ++t) {
-            const float2 u = sample_control(c, V, k, t);
-            u_out[(size_t)t * c.K + k] = u;
-            acc += smooth_cost(c, s);
-            cnt += obstacle_hits(tab, n_oct, s.x, s.y);
-            if (c.use_ctrl) {
-                const float term = __fmaf_rn(V[2 * t] * c.inv_var0, u.x, V[2 * t + 1] * c.inv_var1 * u.y);
-                ctrl = __fmaf_rn(c.gamma, term, ctrl);
-            }
-            bicycle_step(s, c.dt * u.x, tanf(u.y) * c.inv_wheelbase, c.dt);
-        }
-        float S = __fmaf_rn(c.c_obs, (float)cnt, acc);
-        if (c.use_ctrl) S += ctrl;
-        if (c.use_term) S += terminal_cost(c, s);
-        S_out[k] = S;
-        return;
-    }
-
-    // ---- disturbed rollouts: one lane per (sample, draw) ----
-    const int wg = blockIdx.x - c.n_nom_wg;
-    const int spb = c.spb, M = c.M, T = c.T;
-    for (int idx = tid; idx < spb * T; idx += blockDim.x) {
-        const int sl = idx / T;
-        const int t = idx - sl * T;
-        const int kk = wg * spb + sl;
-        float2 cu = make_float2(0.0f, 0.0f);
-        if (kk < c.K) {
-            const float2 u = sample_control(c, V, kk, t);
-            cu = make_float2(c.dt * u.x, tanf(u.y) * c.inv_wheelbase);
-        }
-        ctl[idx] = cu;
-    }
-    __syncthreads();
-
-    const int sl = tid / M;
-    const int m = tid - sl * M;
-    const int k = wg * spb + sl;
-    const bool active = (sl < spb) && (k < c.K);
-    float L = 0.0f;
-    if (active) {
-        const float2* ck = ctl + sl * T;
-        State s{0.0f, 0.0f, c.psi0, c.v0};
-        float acc = 0.0f;
-        int cnt = 0;
-        for (int t = 0; t < T; ++t) {
-            acc += smooth_cost(c, s);
-            cnt += obstacle_hits(tab, n_oct, s.x, s.y);
-            if (t + 1 < T) {  // the last draw cannot reach the risk cost
-                const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-                const float4 w = disturbance<kNoise>(c, r);
-                const float2 cc = ck[t];
-                bicycle_step(s, cc.x, cc.y, c.dt);
-                s.x += w.x;
-                s.y += w.y;
-                s.psi += w.z;
-                s.v += w.w;
-            }
-        }
-        L = __fmaf_rn(c.c_obs, (float)cnt, acc);
-        if (c.debug) L_out[(size_t)k * M + m] = L;
-    }
-    if (sl < spb) {
-        vals[tid] = L;
-        tail[tid] = __builtin_nanf("");
-    }
-    const float cv = cvar_epilogue(vals, tail, means, spb, M, c.n_tail, c.scale_risk, c.B);
-    if (active && m == 0) cvar_out[k] = cv;
+    rollout_body<kNoise>(c, tab, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem);
 }
 
-// Block-wide reductions over 256 threads (4 waves), fixed order.
-__device__ __forceinline__ float block_min_256(float v, float* red) {
-    v = wave_min(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    return fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
-}
-
-__device__ __forceinline__ float block_sum_256(float v, float* red) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    return (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// Weights and update (Eq. 14-17 and Eq. 4), one launch of G workgroups of
-// 256 threads, each owning a chunk of up to 256 samples:
-//  1. S~ = S + J_C per sample; the chunk's minimum beta_b, its weights
-//     exp(-(S~ - beta_b)/lambda) and their sum Z_b;
-//  2. the chunk's weighted control sums N_b[t] = sum_k w_k u_{k,t}, thread
-//     (t, part) summing a contiguous slice of the chunk, the slices then added
-//     in order;
-//  3. the partials (beta_b, Z_b, N_b) go to the workspace; the workgroup that
-//     finishes last (an acquire-release counter, which it resets for the next
-//     launch) merges them: beta = min beta_b, scale_b = exp(-(beta_b -
-//     beta)/lambda), V+ = sum_b scale_b N_b / sum_b scale_b Z_b, then writes V
-//     (shifted when asked), the first command and, in debug mode, w_hat.
-// No workgroup waits for another, and every sum runs in a fixed order.
-// LDS (dynamic): w[256] | slice sums [parts][2T] | scale[G] | vp[2T].
 __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
                                                 const float* __restrict__ cvar, const float2* __restrict__ u,
                                                 float* __restrict__ S_tilde, float* part, unsigned* counter,
@@ -202,99 +45,8 @@ __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, c
     extern __shared__ float ush[];
     __shared__ float red[4];
     __shared__ int is_last;
-    const int T = c.T, K = c.K;
-    float* wsh = ush;
-    float* psh = wsh + 256;
-    const int tid = threadIdx.x;
-    const int b = blockIdx.x;
-    const int k0 = b * 256;
-    const int n = min(256, K - k0);
-    const int stride = 2 + 2 * T;
-
-    // 1. modified costs and chunk weights
-    float st = __builtin_inff();
-    if (tid < n) {
-        const float cv = cvar[k0 + tid];
-        const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
-        st = S[k0 + tid] + jc;                             // Eq. 16
-        S_tilde[k0 + tid] = st;
-    }
-    const float beta_b = block_min_256(st, red);
-    const float w = (tid < n) ? expf(-(st - beta_b) / c.lambda) : 0.0f;
-    wsh[tid] = w;
-    const float Z_b = block_sum_256(w, red);  // also publishes wsh
-
-    // 2. weighted control sums over slices of the chunk
-    const int slice = (n + parts - 1) / parts;
-    for (int idx = tid; idx < T * parts; idx += 256) {
-        const int t = idx % T;
-        const int pr = idx / T;
-        const int ka = pr * slice, kb = min(n, ka + slice);
-        const float2* ut = u + (size_t)t * K + k0;
-        float ax = 0.0f, ay = 0.0f;
-        for (int k = ka; k < kb; ++k) {
-            const float2 uu = ut[k];
-            ax = __fmaf_rn(wsh[k], uu.x, ax);
-            ay = __fmaf_rn(wsh[k], uu.y, ay);
-        }
-        psh[(size_t)pr * 2 * T + 2 * t] = ax;
-        psh[(size_t)pr * 2 * T + 2 * t + 1] = ay;
-    }
-    __syncthreads();
-    float* pb = part + (size_t)b * stride;
-    for (int j = tid; j < 2 * T; j += 256) {
-        float acc = 0.0f;
-        for (int pr = 0; pr < parts; ++pr) acc += psh[(size_t)pr * 2 * T + j];
-        pb[2 + j] = acc;
-    }
-    if (tid == 0) {
-        pb[0] = beta_b;
-        pb[1] = Z_b;
-    }
-
-    // 3. the last workgroup to finish merges every chunk
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (done == (unsigned)(G - 1));
-        if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-
-    float* scale = psh;               // reuses the slice sums
-    float* vp = scale + G;
-    float bmin = __builtin_inff();
-    for (int bb = tid; bb < G; bb += 256) bmin = fminf(bmin, part[(size_t)bb * stride]);
-    const float beta = block_min_256(bmin, red);
-    float z = 0.0f;
-    for (int bb = tid; bb < G; bb += 256) {
-        const float sc = expf(-(part[(size_t)bb * stride] - beta) / c.lambda);
-        scale[bb] = sc;
-        z = __fmaf_rn(part[(size_t)bb * stride + 1], sc, z);
-    }
-    const float Z = block_sum_256(z, red);  // also publishes scale
-    const float invZ = 1.0f / Z;
-    for (int j = tid; j < 2 * T; j += 256) {
-        float acc = 0.0f;
-        for (int bb = 0; bb < G; ++bb) acc = __fmaf_rn(part[(size_t)bb * stride + 2 + j], scale[bb], acc);
-        vp[j] = acc * invZ;
-    }
-    __syncthreads();
-    const int shift = (c.flags & 2u) != 0;
-    for (int j = tid; j < 2 * T; j += 256) {
-        int src = j;
-        if (shift) src = min(j + 2, 2 * T - 2 + (j & 1));
-        V[j] = vp[src];
-    }
-    if (tid < 2) {
-        u0[tid] = vp[tid];
-        if (u0_host) u0_host[tid] = vp[tid];  // mapped pinned host memory
-    }
-    if (c.debug) {
-        for (int k = tid; k < K; k += 256) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
-    }
+    update_body(c, blockIdx.x, G, parts, S, cvar, u, S_tilde, part, counter, V, u0, u0_host, w_hat, ush, red,
+                &is_last);
 }
 
 // ---- stage kernels (same device functions as the fused step) ----

@@ -27,6 +27,47 @@ struct StepBuffers {
     float* u0_host;     // 2 floats of mapped pinned host memory, or null
 };
 
+// One controller of a batch, in device memory: its step constants (the static
+// part written at creation, the per-step part by k_batch_prep) and buffers.
+struct BatchCtl {
+    StepConst c;
+    const float4* obs;
+    float4* tab;
+    float* V;
+    float2* u;
+    float* S;
+    float* cvar;
+    float* S_tilde;
+    float* w_hat;
+    float* L;
+    float* part;
+    unsigned* counter;
+    float* u0;
+    float* u0_host;  // mapped pinned output, 2 floats
+    int32_t G, parts;
+    float track[4];  // ellipse centre and semi-axes, for the per-step constants
+};
+
+// Per-step inputs of one controller, in mapped pinned host memory.
+struct BatchInput {
+    float x0[4];
+    uint32_t step_idx;
+    uint32_t pad[3];
+};
+
+struct BatchLaunch {
+    BatchCtl* ctls;
+    const BatchInput* inputs;  // device address of the mapped inputs
+    const int2* items;         // rollout items (controller, workgroup), in queue order
+    const int2* uitems;        // update items (controller, chunk)
+    unsigned* queue;           // 2 counters, zero between launches
+    int n_ctl, n_items, n_uitems, grid_rollout;
+    size_t lds_rollout, lds_update;
+};
+
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream);
+hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout);
+
 int update_parts(int T);
 size_t update_lds_bytes(int T, int G);
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,

@@ -19,6 +19,8 @@ Presets (sizes in the notation K samples, T horizon steps, M draws per sample):
   p0   the paper's own controller settings (T=30, K=1024, M=300, lambda=0.35,
        eta=0.2, A=10, alpha=0.9, C_u=0.5, running-cost weights 2 / 1 / 0.1,
        terminal weights 0.6 / 2) on a 0.6 m wide oval with a 10.9 m centreline
+  make_batch  64 controllers of uneven size (K multiple of 256 up to 8192,
+       T 20-100, M 8-128, 10-200 obstacles) for batched serving
 All floating values are rounded to float32 by both consumers.
 """
 from __future__ import annotations
@@ -161,3 +163,28 @@ def random_V(T: int, seed: int, scale=(1.0, 0.2)) -> np.ndarray:
 def plant_noise_counter(j: int) -> tuple[int, int, int, int]:
     """Philox counter of the host plant's disturbance at closed-loop step j."""
     return (0, 0xFFFFFFFE, 0xFFFFFFFF, j & 0xFFFFFFFF)
+
+
+def make_batch(n: int = 64, seed: int = 5, k_range=(256, 8192), t_range=(20, 100), m_range=(8, 128),
+               obs_range=(10, 200)) -> list[dict]:
+    """Worlds of n independent controllers of uneven size (batched serving):
+    K a multiple of 256 in k_range, T in t_range, M in m_range and n_obs in
+    obs_range, each uniform; every controller drives its own obstacle field on
+    the 100 x 40 m oval from its own start angle, with its own Philox key."""
+    rng = np.random.default_rng(seed)
+    worlds = []
+    for i in range(n):
+        K = 256 * int(rng.integers(k_range[0] // 256, k_range[1] // 256 + 1))
+        T = int(rng.integers(t_range[0], t_range[1] + 1))
+        M = int(rng.integers(m_range[0], m_range[1] + 1))
+        n_obs = int(rng.integers(obs_range[0], obs_range[1] + 1))
+        th = float(rng.uniform(0.0, 2.0 * math.pi))
+        a, b = 50.0, 20.0
+        x0 = (a * math.cos(th), b * math.sin(th),
+              math.atan2(b * math.cos(th), -a * math.sin(th)), float(rng.uniform(3.0, 8.0)))
+        p = _preset(1000 + i, K=K, T=T, M=M, lam=0.5, v_ref=8.0, track=(0.0, 0.0, a, b, 3.0), shift=True)
+        wrng = np.random.default_rng(seed * 1000 + i)
+        obs = _oval_obstacles(wrng, n_obs, x0, p["track"], 3.0, (0.5, 1.5), 15.0)
+        worlds.append(dict(name="batch%d" % i, params=p, obstacles=obs.reshape(-1, 3),
+                           x0=np.asarray(x0, dtype=np.float32), V0=np.zeros((T, 2), dtype=np.float32)))
+    return worlds

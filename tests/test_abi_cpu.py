@@ -167,3 +167,31 @@ def test_stage_entries_validate_first(L):
     assert L.mppi_cvar(fake, 4, 16, 0.9, -2.0, fake, None) == MPPI_EINVAL
     assert L.mppi_cvar(None, 4, 16, 0.9, 1.0, fake, None) == MPPI_EINVAL
     assert L.mppi_cvar(fake, 0, 16, 0.9, 1.0, fake, None) == MPPI_OK
+
+
+def test_batch_validation_before_any_device_call(L):
+    ws = W.make_batch(4, k_range=(256, 512), t_range=(10, 20))
+    P = (R.Params * 4)(*[R.make_params(w["params"], len(w["obstacles"])) for w in ws])
+    nb = L.mppi_batch_workspace_bytes(4, P)
+    assert nb > 0 and nb % 256 == 0
+    assert L.mppi_batch_workspace_bytes(0, P) == 0
+    bad = (R.Params * 1)(R.make_params(dict(ws[0]["params"], M=300), 5))
+    assert L.mppi_batch_workspace_bytes(1, bad) == 0
+    assert "exceeds 256" in R.last_error()
+    bad = (R.Params * 1)(R.make_params(dict(ws[0]["params"], alpha=2.0), 5))
+    assert L.mppi_batch_workspace_bytes(1, bad) == 0
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.mppi_batch_create(4, P, None, None, fake, nb, None, ctypes.byref(h)) == MPPI_EINVAL
+    assert L.mppi_batch_create(4, P, None, None, fake, nb, None, None) == MPPI_EINVAL
+    assert L.mppi_batch_step(None, None, None, None, None) == MPPI_EINVAL
+    assert L.mppi_batch_destroy(None) == MPPI_OK
+    assert L.mppi_batch_autotune(None, 1, None, None, None) == MPPI_EINVAL
+
+
+def test_batch_workspace_covers_every_controller(L):
+    ws = W.make_batch(8)
+    P = (R.Params * 8)(*[R.make_params(w["params"], len(w["obstacles"])) for w in ws])
+    total = L.mppi_batch_workspace_bytes(8, P)
+    single = sum(L.mppi_workspace_bytes(ctypes.byref(P[i])) for i in range(8))
+    assert total > single
