@@ -57,7 +57,8 @@ enum {
 enum {
     MPPI_F_DEBUG = 1u,            /* also write L (K x M) and normalised weights */
     MPPI_F_SHIFT = 2u,            /* V <- V+ shifted left by one step, last repeated */
-    MPPI_F_ALLOW_ZERO_NOISE = 4u  /* accept zero variances (then gamma must be 0) */
+    MPPI_F_ALLOW_ZERO_NOISE = 4u, /* accept zero variances (then gamma must be 0) */
+    MPPI_F_GRAD = 8u              /* workspace also holds the buffers of mppi_grad */
 };
 
 /* Library limits (MPPI_EUNSUPPORTED beyond them). */
@@ -143,6 +144,30 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
  * Enqueues three kernels on `stream` and returns. */
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
+
+/* Free energy of the sampled costs and its gradient with respect to V, for
+ * differentiating through one controller step (Eq. 2, with the modified
+ * costs of Eq. 14-16 and the weights of Eq. 17; noise held fixed):
+ *   J(V) = -lambda log((1/K) sum_k exp(-S~_k(V) / lambda)),
+ *   dJ/dV = sum_k w_hat_k dS~_k/dV,
+ *   dS~_k = dS_k + A 1[CVaR_k > C_u] (1/n_tail) sum_{m in tail_k}
+ *           (B dL_{k,m} + (1 - B) dLbar_k),
+ * where n_tail = M - ceil(alpha M) + 1 and the derivative of every indicator
+ * (collisions, the C_u test, tail membership, the box clamp) is taken as zero:
+ * du/dv is 1 strictly inside the control box for the (1 - eta) K samples
+ * that follow V, else 0.  The handle must have been created with
+ * MPPI_F_GRAD in its flags (MPPI_EINVAL otherwise).
+ *   x0, step_idx  as for mppi_step (the same samples and draws).
+ *   V_dev     device, T x 2 floats: the mean sequence; read, not changed.
+ *   grad_dev  device, T x 2 floats: receives dJ/dV.
+ *   J_dev     device, 1 float: receives J; may be NULL.
+ * Recomputes the step's rollouts (forward) and one adjoint recursion per
+ * sample of non-zero weight and per rollout that reaches its gradient: the
+ * nominal one and the tail draws (every draw when B != 1).  Enqueues the
+ * kernels on `stream` and returns; it overwrites the buffers mppi_debug_view
+ * points to. */
+mppi_status mppi_grad(mppi_handle *h, const float x0[4], const float *V_dev, uint32_t step_idx,
+                      float *grad_dev, float *J_dev, void *stream);
 
 /* Destroys the host handle (NULL is accepted); the workspace stays the
  * caller's.  Waits for nothing: the caller must not free the workspace while

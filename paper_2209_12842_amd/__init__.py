@@ -7,8 +7,10 @@ kernels for gfx950 behind a C ABI (include/ramppi.h), with this thin binding.
     V = ctl.new_V()
     u0 = ctl.step(w["x0"], V, step_idx=0)
 """
-from ._binding import (MPPI_F_ALLOW_ZERO_NOISE, MPPI_F_DEBUG, MPPI_F_SHIFT, Batch, Controller, MppiError, Params,
-                       check, cvar, header_functions, last_error, lib, make_params, normals, philox)
+from ._binding import (MPPI_F_ALLOW_ZERO_NOISE, MPPI_F_DEBUG, MPPI_F_GRAD, MPPI_F_SHIFT, Batch, Controller,
+                       MppiError, Params, check, cvar, free_energy, header_functions, last_error, lib, make_params,
+                       normals, philox)
 
 __all__ = ["Batch", "Controller", "MppiError", "Params", "check", "cvar", "header_functions", "last_error", "lib",
-           "make_params", "normals", "philox", "MPPI_F_DEBUG", "MPPI_F_SHIFT", "MPPI_F_ALLOW_ZERO_NOISE"]
+           "make_params", "normals", "philox", "free_energy", "MPPI_F_DEBUG", "MPPI_F_SHIFT",
+           "MPPI_F_ALLOW_ZERO_NOISE", "MPPI_F_GRAD"]

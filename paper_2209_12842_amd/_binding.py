@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libramppi.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "ramppi.h")
 
 MPPI_OK, MPPI_EINVAL, MPPI_ENOMEM, MPPI_EDEVICE, MPPI_EUNSUPPORTED = 0, -1, -2, -3, -4
-MPPI_F_DEBUG, MPPI_F_SHIFT, MPPI_F_ALLOW_ZERO_NOISE = 1, 2, 4
+MPPI_F_DEBUG, MPPI_F_SHIFT, MPPI_F_ALLOW_ZERO_NOISE, MPPI_F_GRAD = 1, 2, 4, 8
 STATUS_NAMES = {0: "MPPI_OK", -1: "MPPI_EINVAL", -2: "MPPI_ENOMEM", -3: "MPPI_EDEVICE", -4: "MPPI_EUNSUPPORTED"}
 
 
@@ -72,6 +72,8 @@ def lib():
         L.mppi_create.restype = ctypes.c_int
         L.mppi_step.argtypes = [V, P(F), V, U32, P(F), V]
         L.mppi_step.restype = ctypes.c_int
+        L.mppi_grad.argtypes = [V, P(F), V, U32, V, V, V]
+        L.mppi_grad.restype = I32
         L.mppi_destroy.argtypes = [V]
         L.mppi_destroy.restype = ctypes.c_int
         L.mppi_last_error.argtypes = []
@@ -162,11 +164,12 @@ class Controller:
     torch stream of that device."""
 
     def __init__(self, params: dict, obstacles, device="cuda", debug: bool = False,
-                 allow_zero_noise: bool = False):
+                 allow_zero_noise: bool = False, grad: bool = False):
         torch = _torch()
         L = lib()
         obs = np.ascontiguousarray(np.asarray(obstacles, dtype=np.float32).reshape(-1, 3))
-        flags = (MPPI_F_DEBUG if debug else 0) | (MPPI_F_ALLOW_ZERO_NOISE if allow_zero_noise else 0)
+        flags = ((MPPI_F_DEBUG if debug else 0) | (MPPI_F_ALLOW_ZERO_NOISE if allow_zero_noise else 0)
+                 | (MPPI_F_GRAD if grad else 0))
         self.params = dict(params)
         self.p = make_params(params, obs.shape[0], flags)
         nbytes = L.mppi_workspace_bytes(ctypes.byref(self.p))
@@ -209,6 +212,20 @@ class Controller:
         if want_u0:
             return np.array([self._u0[0], self._u0[1]], dtype=np.float32)
         return None
+
+    def free_energy(self, x0, V, step_idx: int):
+        """(J, dJ/dV) on the device for the step's samples and draws with the
+        noise held fixed; needs grad=True at construction.  V is read only."""
+        torch = _torch()
+        if not (V.is_cuda and V.dtype == torch.float32 and V.is_contiguous() and V.numel() == 2 * self.T):
+            raise ValueError("V must be a contiguous float32 CUDA tensor with T x 2 elements")
+        x = self._x0
+        x[0], x[1], x[2], x[3] = (float(v) for v in x0)
+        J = torch.empty((), dtype=torch.float32, device=V.device)
+        g = torch.empty_like(V)
+        check(lib().mppi_grad(self._h, x, V.data_ptr(), int(step_idx) & 0xFFFFFFFF, g.data_ptr(), J.data_ptr(),
+                              torch.cuda.current_stream(V.device).cuda_stream))
+        return J, g
 
     def debug(self) -> dict:
         """Views into the workspace: u (T, K, 2), S, L (K, M), cvar, S_tilde,
@@ -373,3 +390,36 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _free_energy_fn():
+    torch = _torch()
+
+    class FreeEnergy(torch.autograd.Function):
+        """J(V) of a controller step as a differentiable function of V (the
+        sampled controls and disturbances held fixed); forward and backward
+        both run in the library's kernels."""
+
+        @staticmethod
+        def forward(ctx, V, controller, x0, step_idx):
+            J, g = controller.free_energy(x0, V.detach().contiguous(), step_idx)
+            ctx.save_for_backward(g)
+            return J
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            return gJ * g, None, None, None
+
+    return FreeEnergy
+
+
+_FREE_ENERGY = None
+
+
+def free_energy(V, controller: "Controller", x0, step_idx: int):
+    """Differentiable J(V) (torch autograd) of one controller step."""
+    global _FREE_ENERGY
+    if _FREE_ENERGY is None:
+        _FREE_ENERGY = _free_energy_fn()
+    return _FREE_ENERGY.apply(V, controller, x0, step_idx)

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libramppi.so")
-SOURCES = ["kernels.hip", "batch.hip", "api.hip"]
+SOURCES = ["kernels.hip", "batch.hip", "grad.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

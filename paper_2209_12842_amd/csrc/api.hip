@@ -74,7 +74,11 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, total;
+    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, counter;
+    // gradient buffers (MPPI_F_GRAD)
+    size_t ranks, tail_idx, act_list, n_act, J, states, rows, rpart, gcounter;
+    int R, stride, n_lane_blocks;
+    size_t total;
 };
 
 Layout layout(const mppi_params* p) {
@@ -92,6 +96,24 @@ Layout layout(const mppi_params* p) {
     l.part = o;    o += align_up(4 * (size_t)g.G * (2 + 2 * (size_t)p->T));
     l.u0 = o;      o += align_up(8);
     l.counter = o; o += align_up(4);
+    l.ranks = l.tail_idx = l.act_list = l.n_act = l.J = l.states = l.rows = l.rpart = l.gcounter = 0;
+    l.R = l.stride = l.n_lane_blocks = 0;
+    if (p->flags & MPPI_F_GRAD) {
+        int n_tail = 0, n_warm = 0;
+        derived_counts(p, &n_tail, &n_warm);
+        l.R = 1 + (p->B != 1.0f ? p->M : n_tail);
+        l.n_lane_blocks = (int)(((int64_t)p->K * l.R + 255) / 256);
+        l.stride = 256 * l.n_lane_blocks;
+        l.ranks = o;    o += align_up(4 * (size_t)p->K * p->M);
+        l.tail_idx = o; o += align_up(4 * (size_t)p->K * n_tail);
+        l.act_list = o; o += align_up(4 * (size_t)p->K);
+        l.n_act = o;    o += align_up(4);
+        l.J = o;        o += align_up(4);
+        l.states = o;   o += align_up(16 * (size_t)p->T * l.stride);
+        l.rows = o;     o += align_up(4 * 2 * (size_t)p->T * l.stride);
+        l.rpart = o;    o += align_up(4 * 2 * (size_t)p->T * l.n_lane_blocks);
+        l.gcounter = o; o += align_up(4);
+    }
     l.total = o;
     return l;
 }
@@ -199,6 +221,29 @@ struct mppi_handle {
     int n_timed;
 };
 
+namespace {
+
+ramppi::StepBuffers step_buffers(const mppi_handle* h, float* V_dev) {
+    ramppi::StepBuffers bufs;
+    bufs.obs = reinterpret_cast<const float4*>(h->ws + h->l.obs);
+    bufs.tab = reinterpret_cast<float4*>(h->ws + h->l.tab);
+    bufs.V = V_dev;
+    bufs.Vout = V_dev;
+    bufs.u = reinterpret_cast<float2*>(h->ws + h->l.u);
+    bufs.S = reinterpret_cast<float*>(h->ws + h->l.S);
+    bufs.cvar = reinterpret_cast<float*>(h->ws + h->l.cvar);
+    bufs.S_tilde = reinterpret_cast<float*>(h->ws + h->l.S_tilde);
+    bufs.w_hat = reinterpret_cast<float*>(h->ws + h->l.w_hat);
+    bufs.L = reinterpret_cast<float*>(h->ws + h->l.L);
+    bufs.part = reinterpret_cast<float*>(h->ws + h->l.part);
+    bufs.u0 = reinterpret_cast<float*>(h->ws + h->l.u0);
+    bufs.counter = reinterpret_cast<unsigned*>(h->ws + h->l.counter);
+    bufs.u0_host = nullptr;
+    return bufs;
+}
+
+}  // namespace
+
 extern "C" {
 
 mppi_status mppi_validate(const mppi_params* p) {
@@ -206,7 +251,7 @@ mppi_status mppi_validate(const mppi_params* p) {
     if (p->K < 1 || p->T < 1 || p->M < 1 || p->n_obs < 0)
         return fail(MPPI_EINVAL, "sizes must satisfy K, T, M >= 1 and n_obs >= 0 (got K=%d T=%d M=%d n_obs=%d)",
                     p->K, p->T, p->M, p->n_obs);
-    if (p->flags & ~(uint32_t)(MPPI_F_DEBUG | MPPI_F_SHIFT | MPPI_F_ALLOW_ZERO_NOISE))
+    if (p->flags & ~(uint32_t)(MPPI_F_DEBUG | MPPI_F_SHIFT | MPPI_F_ALLOW_ZERO_NOISE | MPPI_F_GRAD))
         return fail(MPPI_EINVAL, "unknown flag bits 0x%x", p->flags);
     if (!(finite(p->dt) && p->dt > 0)) return fail(MPPI_EINVAL, "dt must be finite and > 0");
     if (!(finite(p->wheelbase) && p->wheelbase > 0)) return fail(MPPI_EINVAL, "wheelbase must be finite and > 0");
@@ -248,6 +293,8 @@ mppi_status mppi_validate(const mppi_params* p) {
     if (p->T > MPPI_MAX_T) return fail(MPPI_EUNSUPPORTED, "T = %d exceeds %d", p->T, MPPI_MAX_T);
     if (p->K > kMaxK) return fail(MPPI_EUNSUPPORTED, "K = %d exceeds %d", p->K, kMaxK);
     if ((int64_t)p->K * p->M > (int64_t)INT32_MAX) return fail(MPPI_EUNSUPPORTED, "K * M exceeds 2^31 - 1");
+    if ((p->flags & MPPI_F_GRAD) && (int64_t)p->K * (1 + p->M) > (int64_t)INT32_MAX / 4)
+        return fail(MPPI_EUNSUPPORTED, "K (1 + M) too large for the gradient buffers");
     const Geometry g = geometry(p);
     if (g.lds_rollout > kMaxLdsBytes)
         return fail(MPPI_EUNSUPPORTED, "rollout LDS need %zu B exceeds %zu B (reduce T or M)", g.lds_rollout,
@@ -315,6 +362,7 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     }
     e = hipMemcpyAsync(h->ws + l.obs, staged.data(), 16 * (size_t)p->n_obs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.counter, 0, 4, s);
+    if (e == hipSuccess && (p->flags & MPPI_F_GRAD)) e = hipMemsetAsync(h->ws + l.gcounter, 0, 4, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipHostFree(h->u0_pinned);
@@ -350,20 +398,7 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     fill_static(&c, p, g, h->n_tail, h->n_warm);
     fill_dynamic(&c, p, x0, step_idx);
 
-    ramppi::StepBuffers bufs;
-    bufs.obs = reinterpret_cast<const float4*>(h->ws + h->l.obs);
-    bufs.tab = reinterpret_cast<float4*>(h->ws + h->l.tab);
-    bufs.V = V_dev;
-    bufs.Vout = V_dev;
-    bufs.u = reinterpret_cast<float2*>(h->ws + h->l.u);
-    bufs.S = reinterpret_cast<float*>(h->ws + h->l.S);
-    bufs.cvar = reinterpret_cast<float*>(h->ws + h->l.cvar);
-    bufs.S_tilde = reinterpret_cast<float*>(h->ws + h->l.S_tilde);
-    bufs.w_hat = reinterpret_cast<float*>(h->ws + h->l.w_hat);
-    bufs.L = reinterpret_cast<float*>(h->ws + h->l.L);
-    bufs.part = reinterpret_cast<float*>(h->ws + h->l.part);
-    bufs.u0 = reinterpret_cast<float*>(h->ws + h->l.u0);
-    bufs.counter = reinterpret_cast<unsigned*>(h->ws + h->l.counter);
+    ramppi::StepBuffers bufs = step_buffers(h, V_dev);
     bufs.u0_host = u0_host ? h->u0_pinned_dev : nullptr;
 
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_end = nullptr;
@@ -387,6 +422,54 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         u0_host[0] = h->u0_pinned[0];
         u0_host[1] = h->u0_pinned[1];
     }
+    return MPPI_OK;
+}
+
+mppi_status mppi_grad(mppi_handle* h, const float x0[4], const float* V_dev, uint32_t step_idx, float* grad_dev,
+                      float* J_dev, void* stream) {
+    if (!h) return fail(MPPI_EINVAL, "handle is NULL");
+    if (!(h->p.flags & MPPI_F_GRAD)) return fail(MPPI_EINVAL, "the handle was created without MPPI_F_GRAD");
+    if (!x0 || !V_dev || !grad_dev) return fail(MPPI_EINVAL, "x0, V_dev or grad_dev is NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!finite(x0[i])) return fail(MPPI_EINVAL, "x0[%d] is not finite", i);
+    const mppi_params& p = h->p;
+    const Geometry& g = h->g;
+    const Layout& l = h->l;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    ramppi::StepConst c;
+    fill_static(&c, p, g, h->n_tail, h->n_warm);
+    fill_dynamic(&c, p, x0, step_idx);
+    c.grad = 1;
+    c.debug = 0;
+
+    ramppi::StepBuffers bufs = step_buffers(h, const_cast<float*>(V_dev));
+    bufs.Vout = nullptr;
+    ramppi::GradArgs a;
+    a.V = V_dev;
+    a.u = bufs.u;
+    a.cvar = bufs.cvar;
+    a.w_hat = bufs.w_hat;
+    a.act_list = reinterpret_cast<const int*>(h->ws + l.act_list);
+    a.n_act = reinterpret_cast<const int*>(h->ws + l.n_act);
+    a.tail_idx = reinterpret_cast<const int*>(h->ws + l.tail_idx);
+    a.ranks = reinterpret_cast<const int*>(h->ws + l.ranks);
+    a.ranks_w = reinterpret_cast<int*>(h->ws + l.ranks);
+    a.tail_w = reinterpret_cast<int*>(h->ws + l.tail_idx);
+    a.states = reinterpret_cast<float4*>(h->ws + l.states);
+    a.rows = reinterpret_cast<float*>(h->ws + l.rows);
+    a.rpart = reinterpret_cast<float*>(h->ws + l.rpart);
+    a.counter = reinterpret_cast<unsigned*>(h->ws + l.gcounter);
+    a.grad_out = grad_dev;
+    a.R = l.R;
+    a.stride = l.stride;
+    ramppi::GradOut go;
+    go.J = J_dev ? J_dev : reinterpret_cast<float*>(h->ws + l.J);
+    go.act_list = reinterpret_cast<int*>(h->ws + l.act_list);
+    go.n_act = reinterpret_cast<int*>(h->ws + l.n_act);
+    const hipError_t e =
+        ramppi::launch_grad(c, bufs, a, go, g.block, g.lds_rollout, g.G, g.lds_update, l.n_lane_blocks, s);
+    if (e != hipSuccess) return hip_fail(e, "gradient launch");
     return MPPI_OK;
 }
 

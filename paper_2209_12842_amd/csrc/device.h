@@ -98,6 +98,7 @@ struct StepConst {
     float fx, fy;        // frame origin (the start position)
     uint32_t key0, key1, step_idx, flags;
     int32_t use_bdry, use_term, use_ctrl, scale_risk, debug;
+    int32_t grad;        // record tail ranks for the gradient of the free energy
 };
 
 struct State {
@@ -231,7 +232,7 @@ __device__ __forceinline__ float terminal_cost(const StepConst& c, const State& 
 // smaller index, so ranks are a permutation of 0..M-1 and the n_tail largest
 // values land, in descending order, in tail[0..n_tail-1].  The caller
 // synchronises the workgroup between this and tail_sum.
-__device__ __forceinline__ void tail_rank_scatter(const float* vals, float* tail, int M, int m, int n_tail) {
+__device__ __forceinline__ int tail_rank_scatter(const float* vals, float* tail, int M, int m, int n_tail) {
     const float v = vals[m];
     int rank = 0;
     for (int j = 0; j < M; ++j) {
@@ -239,6 +240,7 @@ __device__ __forceinline__ void tail_rank_scatter(const float* vals, float* tail
         rank += (o > v) | ((o == v) & (j < m));
     }
     if (rank < n_tail) tail[rank] = v;
+    return rank;
 }
 
 __device__ __forceinline__ float tail_sum(const float* tail, int n_tail) {
@@ -259,6 +261,47 @@ __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// ---- gradients (adjoint of one rollout) ----
+
+// Gradient of the smooth running-cost terms with respect to the state
+// (the obstacle indicator contributes nothing): c_dev e^2, c_v (v - v_ref)^2
+// and c_bdry mu_bdry(d), with e = G / |grad G| and d = hw - |e|.
+__device__ __forceinline__ float4 smooth_cost_grad(const StepConst& c, const State& s) {
+    const float X = s.x + c.tox;
+    const float Y = s.y + c.toy;
+    const float xa = X * c.inv_a;
+    const float yb = Y * c.inv_b;
+    const float G = __fmaf_rn(xa, xa, __fmaf_rn(yb, yb, -1.0f));
+    const float gx = X * c.g_a;
+    const float gy = Y * c.g_b;
+    const float gn2 = fmaxf(__fmaf_rn(gx, gx, gy * gy), 1e-24f);
+    const float rgn = rsqrtf(gn2);
+    const float e = G * rgn;
+    const float k3 = G * rgn * rgn * rgn;          // G / |grad G|^3
+    const float deX = gx * rgn - k3 * gx * c.g_a;  // de/dX (g_a = 2/a^2)
+    const float deY = gy * rgn - k3 * gy * c.g_b;
+    float fx = 2.0f * c.c_dev * e * deX;
+    float fy = 2.0f * c.c_dev * e * deY;
+    if (c.use_bdry) {
+        const float d = c.hw - fabsf(e);
+        const float dmu = -100.0f * 0.318309886183790671538f / __fmaf_rn(1e4f * d, d, 1.0f);
+        const float sg = (e > 0.0f) ? -1.0f : ((e < 0.0f) ? 1.0f : 0.0f);  // d(d)/de = -sign(e)
+        fx = __fmaf_rn(c.c_bdry * dmu * sg, deX, fx);
+        fy = __fmaf_rn(c.c_bdry * dmu * sg, deY, fy);
+    }
+    return make_float4(fx, fy, 0.0f, 2.0f * c.c_v * (s.v - c.v_ref));
+}
+
+// Gradient of the terminal cost (Eq. 23) with respect to x_T.
+__device__ __forceinline__ float4 terminal_cost_grad(const StepConst& c, const State& s) {
+    const float xi = (s.x + c.tox) * c.inv_a;
+    const float et = (s.y + c.toy) * c.inv_b;
+    const float r2 = __fmaf_rn(xi, xi, et * et);
+    if (!(r2 > 0.0f)) return make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float k = -c.c5 * c.half_ab / r2;
+    return make_float4(k * (-et * c.inv_a), k * (xi * c.inv_b), 0.0f, 0.0f);
 }
 
 }  // namespace ramppi

@@ -32,9 +32,10 @@ template <int kNoise>
 __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct* __restrict__ tab,
                                                   const float* __restrict__ V, float2* __restrict__ u_out,
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
-                                                  float* __restrict__ L_out) {
+                                                  float* __restrict__ L_out, int* __restrict__ ranks,
+                                                  int* __restrict__ tail_idx) {
     extern __shared__ float2 smem[];
-    rollout_body<kNoise>(c, tab, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem);
+    rollout_body<kNoise>(c, tab, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx);
 }
 
 __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
@@ -88,6 +89,28 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
 
 // ---- launchers ----
 
+void launch_obstacle_frame(const StepConst& c, const StepBuffers& b, hipStream_t stream) {
+    if (c.n_obs > 0)
+        hipLaunchKernelGGL(k_obstacle_frame, dim3((c.n_obs + 255) / 256), dim3(256), 0, stream, b.obs, c.n_obs,
+                           c.fx, c.fy, b.tab);
+}
+
+hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
+                          hipStream_t stream, int* ranks, int* tail_idx) {
+    const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
+    const dim3 grid(c.n_nom_wg + n_dist_wg);
+    if (c.noise_kind == 1)
+        hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
+                           ranks, tail_idx);
+    else if (c.noise_kind == 2)
+        hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
+                           ranks, tail_idx);
+    else
+        hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
+                           ranks, tail_idx);
+    return hipGetLastError();
+}
+
 int update_parts(int T) { return T >= 256 ? 1 : 256 / T; }
 
 size_t update_lds_bytes(int T, int G) {
@@ -99,18 +122,9 @@ size_t update_lds_bytes(int T, int G) {
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
                        size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
     const int n_dist_wg = (c.K + c.spb - 1) / c.spb;
-    if (c.n_obs > 0)
-        hipLaunchKernelGGL(k_obstacle_frame, dim3((c.n_obs + 255) / 256), dim3(256), 0, stream, b.obs, c.n_obs,
-                           c.fx, c.fy, b.tab);
+    launch_obstacle_frame(c, b, stream);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
-    const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
-    const dim3 grid(c.n_nom_wg + n_dist_wg);
-    if (c.noise_kind == 1)
-        hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L);
-    else if (c.noise_kind == 2)
-        hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L);
-    else
-        hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L);
+    (void)launch_rollout(c, b, block, lds_rollout, n_dist_wg, stream, nullptr, nullptr);
     if (ev_mid) (void)hipEventRecord(ev_mid, stream);
     hipLaunchKernelGGL(k_update, dim3(G), dim3(256), lds_update, stream, c, G, update_parts(c.T), b.S, b.cvar, b.u,
                        b.S_tilde, b.part, b.counter, b.Vout, b.u0, b.u0_host, b.w_hat);

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "device.h"
+#include "step_device.h"
 
 namespace ramppi {
 
@@ -68,10 +69,36 @@ struct BatchLaunch {
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream);
 hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout);
 
+// Buffers of the gradient of the free energy (see grad.hip).
+struct GradArgs {
+    const float* V;
+    const float2* u;
+    const float* cvar;
+    const float* w_hat;
+    const int* act_list;
+    const int* n_act;
+    const int* tail_idx;
+    const int* ranks;
+    int* ranks_w;       // written by the forward rollout
+    int* tail_w;
+    float4* states;     // T x stride recomputed states
+    float* rows;        // 2T x stride gradient rows
+    float* rpart;       // blocks x 2T
+    unsigned* counter;
+    float* grad_out;    // T x 2
+    int R;              // lanes per weighted sample: nominal + tail (or + all draws)
+    int stride;         // lane capacity K R
+};
+
 int update_parts(int T);
 size_t update_lds_bytes(int T, int G);
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
                        size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid);
+void launch_obstacle_frame(const StepConst& c, const StepBuffers& b, hipStream_t stream);
+hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
+                          hipStream_t stream, int* ranks, int* tail_idx);
+hipError_t launch_grad(const StepConst& c, const StepBuffers& b, const GradArgs& a, const GradOut& go, int block,
+                       size_t lds_rollout, int G, size_t lds_update, int n_lane_blocks, hipStream_t stream);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t stream);
 hipError_t launch_normals(uint64_t seed, const uint32_t* ctr, float* out, int64_t n, hipStream_t stream);
 hipError_t launch_cvar(const float* L, int K, int M, int spb, int block, int n_tail, int scale_risk, float B,

@@ -6,6 +6,14 @@
 
 namespace ramppi {
 
+// Outputs of the update in gradient mode (the free energy, the list of
+// samples of non-zero weight and its length).
+struct GradOut {
+    float* J;
+    int* act_list;
+    int* n_act;
+};
+
 // One entry of the obstacle table of a step, in the local frame centred on
 // the start position (fx, fy): (-2 cx, -2 cy, r^2 - cx^2 - cy^2, 0) for
 // i < n_obs; entries up to the next multiple of 8 can never be hit (-inf).
@@ -29,7 +37,7 @@ __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs,
 // vals holds the raw risk costs (thread tid owns slot tid for tid < spb * M);
 // returns the CVaR in the m == 0 lane of each sample.
 __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* means, int spb, int M,
-                                               int n_tail, int scale_risk, float B) {
+                                               int n_tail, int scale_risk, float B, int* rank_out = nullptr) {
     const int tid = threadIdx.x;
     const int sl = tid / M;
     const int m = tid - sl * M;
@@ -48,7 +56,10 @@ __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* 
         }
         __syncthreads();
     }
-    if (own) tail_rank_scatter(vals + sl * M, tail + sl * M, M, m, n_tail);
+    if (own) {
+        const int rank = tail_rank_scatter(vals + sl * M, tail + sl * M, M, m, n_tail);
+        if (rank_out) *rank_out = rank;
+    }
     __syncthreads();
     float cv = 0.0f;
     if (own && m == 0) cv = tail_sum(tail + sl * M, n_tail);
@@ -63,7 +74,8 @@ template <int kNoise>
 __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleOct* __restrict__ tab,
                                              const float* __restrict__ V, float2* __restrict__ u_out,
                                              float* __restrict__ S_out, float* __restrict__ cvar_out,
-                                             float* __restrict__ L_out, int item, float2* smem) {
+                                             float* __restrict__ L_out, int item, float2* smem,
+                                             int* __restrict__ ranks = nullptr, int* __restrict__ tail_idx = nullptr) {
     float2* ctl = smem;
     float* vals = reinterpret_cast<float*>(ctl + (size_t)c.spb * c.T);
     float* tail = vals + c.spb * c.M;
@@ -143,8 +155,13 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
         vals[tid] = L;
         tail[tid] = __builtin_nanf("");
     }
-    const float cv = cvar_epilogue(vals, tail, means, spb, M, c.n_tail, c.scale_risk, c.B);
+    int rank = M;
+    const float cv = cvar_epilogue(vals, tail, means, spb, M, c.n_tail, c.scale_risk, c.B, &rank);
     if (active && m == 0) cvar_out[k] = cv;
+    if (c.grad && active) {  // tail membership for the gradient
+        ranks[(size_t)k * M + m] = rank;
+        if (rank < c.n_tail) tail_idx[(size_t)k * c.n_tail + rank] = m;
+    }
 }
 
 // Block-wide reductions over 256 threads (4 waves), fixed order.
@@ -185,7 +202,7 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
                                             float* __restrict__ S_tilde, float* part, unsigned* counter,
                                             float* __restrict__ V, float* __restrict__ u0,
                                             float* __restrict__ u0_host, float* __restrict__ w_hat, float* ush,
-                                            float* red, int* is_last_sh) {
+                                            float* red, int* is_last_sh, const GradOut* go = nullptr) {
     int& is_last = *is_last_sh;
     const int T = c.T, K = c.K;
     float* wsh = ush;
@@ -236,7 +253,9 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         pb[1] = Z_b;
     }
 
-    // 3. the last workgroup to finish merges every chunk
+    // 3. the last workgroup to finish merges every chunk; every thread makes
+    // its own stores visible at device scope before thread 0 signals
+    __threadfence();
     __syncthreads();
     if (tid == 0) {
         const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -266,6 +285,36 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         vp[j] = acc * invZ;
     }
     __syncthreads();
+    if (go) {
+        // gradient mode: V stays as it is; write J = beta - lambda log(Z/K),
+        // every w_hat, and the samples of non-zero weight in increasing order
+        if (tid == 0) *go->J = beta - c.lambda * logf(Z / (float)K);
+        int base = 0;
+        for (int k0b = 0; k0b < K; k0b += 256) {
+            const int k = k0b + tid;
+            float wk = 0.0f;
+            if (k < K) {
+                wk = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
+                w_hat[k] = wk;
+            }
+            const int flag = (k < K) && (wk > 0.0f);
+            // exclusive prefix of the flags in thread order (fixed, so the list is deterministic)
+            const uint64_t ball = __builtin_amdgcn_ballot_w64(flag);
+            const int lane = tid & 63, wv = tid >> 6;
+            const int in_wave = __builtin_popcountll(ball & ((1ull << lane) - 1ull));
+            __syncthreads();
+            if (lane == 0) red[wv] = __int_as_float(__builtin_popcountll(ball));
+            __syncthreads();
+            int before = 0;
+            for (int q = 0; q < wv; ++q) before += __float_as_int(red[q]);
+            const int total = __float_as_int(red[0]) + __float_as_int(red[1]) + __float_as_int(red[2]) +
+                              __float_as_int(red[3]);
+            if (flag) go->act_list[base + before + in_wave] = k;
+            base += total;
+        }
+        if (tid == 0) *go->n_act = base;
+        return;
+    }
     const int shift = (c.flags & 2u) != 0;
     for (int j = tid; j < 2 * T; j += 256) {
         int src = j;
