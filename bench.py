@@ -13,7 +13,18 @@ loop.  Synthetic seeded inputs.  One JSON line on stdout:
   cpu_baseline the FP64 oracle on a bounded sample of the same workload,
                timed on this host's cores
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c1]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c1|c4]
+
+Other legs (one JSON line each, not the default):
+  --workload c5   batched serving: 64 independent controllers of uneven size
+                  in one step call (persistent work-queue kernel replayed
+                  from a HIP graph, autotuned grid), closed loop through the
+                  host plant; compared with 64 sequential single-controller
+                  steps of the same controllers
+  --grad          the free-energy gradient dJ/dV on the workload (default
+                  c4: K = 4096, T = 50, M = 64): evaluations per second, its
+                  cost relative to a plain step, and gradient-corrected steps
+                  against plain steps at equal wall time
 """
 from __future__ import annotations
 
@@ -83,7 +94,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default=None, choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--grad", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-sized device buffer 3 times (a plain copy kernel of "
@@ -97,6 +109,12 @@ def main():
     import torch
     import paper_2209_12842_amd as R
 
+    if args.grad:
+        return run_grad(args, R, torch)
+    if args.workload == "c5":
+        return run_batch(args, R, torch)
+    if args.workload is None:
+        args.workload = "c2"
     world = W.make_world(args.workload)
     p = dict(world["params"])
     p["shift"] = True                      # receding horizon: V <- shifted V+
@@ -174,6 +192,182 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(world)
         out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+    ctl.close()
+
+
+def run_batch(args, R, torch):
+    """64 independent controllers (workloads.make_batch) per step call."""
+    ws = W.make_batch(64)
+    n = len(ws)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    work = sum(w["params"]["K"] * w["params"]["M"] * w["params"]["T"] for w in ws)
+    flops = sum(model_flops(w["params"], len(w["obstacles"])) for w in ws)
+    dt32 = np.array([float(np.float32(w["params"]["dt"])) for w in ws])
+    wb32 = np.array([float(np.float32(w["params"]["wheelbase"])) for w in ws])
+    sw = np.stack([np.sqrt(np.float32(w["params"]["sigma_w"]).astype(np.float64)) for w in ws])
+    n_total = args.warmup + args.steps
+    plant_w = np.random.default_rng(12345).standard_normal((n_total, n, 4)) * sw
+
+    def plant(x, u, j):
+        px, py, psi, v = x[:, 0], x[:, 1], x[:, 2], x[:, 3]
+        u = u.astype(np.float64)
+        return np.stack([px + dt32 * v * np.cos(psi), py + dt32 * v * np.sin(psi),
+                         psi + dt32 * v * np.tan(u[:, 1]) / wb32, v + dt32 * u[:, 0]], axis=1) + plant_w[j]
+
+    x0 = np.stack([w["x0"] for w in ws]).astype(np.float64)
+
+    # 64 sequential single-controller steps per round (no readback between
+    # them; one synchronisation and one gather of the 64 commands per round)
+    ctls = [R.Controller(w["params"], w["obstacles"], device=dev) for w in ws]
+    Vs = [c.new_V() for c in ctls]
+    u0v = [c.debug()["u0"] for c in ctls]
+    x = x0.copy()
+
+    def seq_round(j):
+        nonlocal x
+        for i, c in enumerate(ctls):
+            c.step(x[i], Vs[i], j, want_u0=False)
+        u = torch.stack(u0v).cpu().numpy()
+        x = plant(x, u, j)
+
+    for j in range(args.warmup):
+        seq_round(j)
+    torch.cuda.synchronize()
+    seq_lat = np.empty(args.steps)
+    t0 = time.perf_counter()
+    for j in range(args.steps):
+        s0 = time.perf_counter()
+        seq_round(args.warmup + j)
+        seq_lat[j] = time.perf_counter() - s0
+    seq_elapsed = time.perf_counter() - t0
+    for c in ctls:
+        c.close()
+    del ctls, Vs, u0v
+    torch.cuda.empty_cache()
+
+    b = R.Batch([w["params"] for w in ws], [w["obstacles"] for w in ws], device=dev)
+    x = x0.copy()
+    b.step(x, 0, want_u0=True)
+    wg, order = b.autotune(3)
+    x = x0.copy()
+    for j in range(args.warmup):
+        x = plant(x, b.step(x, j, want_u0=True), j)
+    torch.cuda.synchronize()
+    lat = np.empty(args.steps)
+    t0 = time.perf_counter()
+    for j in range(args.steps):
+        s0 = time.perf_counter()
+        jj = args.warmup + j
+        x = plant(x, b.step(x, jj, want_u0=True), jj)
+        lat[j] = time.perf_counter() - s0
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert np.all(np.isfinite(x))
+    # kernel durations: the same kernels launched directly with HIP events
+    n_k = min(args.steps, 50)
+    b.timing_enable(True)
+    for j in range(n_k):
+        b.step(x, n_total + j, want_u0=False)
+    roll_ms, upd_ms, n_timed = b.timing_read()
+    b.timing_enable(False)
+    b.close()
+
+    roll_avg_s = roll_ms / max(n_timed, 1) * 1e-3
+    achieved_tf = flops / roll_avg_s / 1e12
+    value = work * args.steps / elapsed
+    seq_value = work * args.steps / seq_elapsed
+    out = {
+        "metric": "rollout-steps/s (sum of K*M*T over 64 controllers per batched step), closed loop",
+        "value": value, "unit": "rollout-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (64 seeded worlds: 10-200 obstacles each on a 100 x 40 m oval, Philox noise)",
+        "config": {"workload": "c5: 64 controllers, K multiple of 256 in [256, 8192], T in [20, 100], "
+                               "M in [8, 128]; %d rollout-steps per batched step" % work,
+                   "controllers": n, "autotune": {"wg_per_cu": wg, "order": order}, "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "sequential": {"value": seq_value, "ms_per_step": seq_elapsed / args.steps * 1e3,
+                       "p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
+                       "p99_ms": float(np.percentile(seq_lat, 99) * 1e3)},
+        "speedup_vs_sequential": value / seq_value,
+        "kernel_ms": {"rollout": roll_avg_s * 1e3, "update": upd_ms / max(n_timed, 1),
+                      "measured_over": "%d direct launches after the timed steps" % n_timed},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_batch_rollout",
+                     "model_flops_per_launch": flops},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_grad(args, R, torch):
+    """dJ/dV of the free energy on the workload (default c4)."""
+    name = args.workload or "c4"
+    world = W.make_world(name)
+    p = dict(world["params"])
+    p["shift"] = False
+    obs = world["obstacles"]
+    K, T, M = p["K"], p["T"], p["M"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    x0 = world["x0"]
+    ctl = R.Controller(p, obs, device=dev, grad=True)
+    V = ctl.new_V(W.random_V(T, 4, scale=(1.0, 0.2)))
+
+    def timed(fn, n):
+        for j in range(args.warmup):
+            fn(j)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for j in range(n):
+            fn(args.warmup + j)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    g_ms = timed(lambda j: ctl.free_energy(x0, V, j), args.steps)
+    Vs = V.clone()
+    s_ms = timed(lambda j: ctl.step(x0, Vs, j, want_u0=False), args.steps)
+
+    # equal wall time: plain steps against (step, gradient, correction) rounds
+    # from V = 0 at the start state, each round on fresh noise; both final
+    # sequences are scored by the mean free energy over 16 held-out call
+    # indices (lower is better)
+    def score(Vf):
+        js = [ctl.free_energy(x0, Vf, 1_000_000 + i)[0] for i in range(16)]
+        return float(torch.stack(js).mean().item())
+
+    budget_rounds = 20
+    n_plain = int(round(budget_rounds * (s_ms + g_ms) / s_ms))
+    tau = 0.05
+    Vp = ctl.new_V()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(n_plain):
+        ctl.step(x0, Vp, 10_000 + j, want_u0=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    Vg = ctl.new_V()
+    t0 = time.perf_counter()
+    for j in range(budget_rounds):
+        ctl.step(x0, Vg, 10_000 + j, want_u0=False)
+        _, g = ctl.free_energy(x0, Vg, 20_000 + j)
+        Vg -= tau * g / g.abs().max().clamp_min(1e-30)
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    out = {
+        "metric": "free-energy gradient evaluations/s (dJ/dV, K=%d T=%d M=%d)" % (K, T, M),
+        "value": 1e3 / g_ms, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": g_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded world: %d obstacles on an elliptic track, Philox noise)" % len(obs),
+        "config": {"workload": "%s: K=%d T=%d M=%d n_obs=%d lambda=%g, mppi_grad (forward + adjoint)"
+                               % (name, K, T, M, len(obs), p["lam"]), "parallelism": "single GPU"},
+        "plain_step_ms": s_ms, "gradient_over_step": g_ms / s_ms,
+        "equal_wall_time": {"plain_steps": n_plain, "plain_s": t_plain, "grad_rounds": budget_rounds,
+                            "grad_s": t_grad, "tau": tau, "J_plain": score(Vp), "J_grad_corrected": score(Vg)},
+    }
     print(json.dumps(out), flush=True)
     ctl.close()
 

@@ -251,6 +251,15 @@ mppi_status mppi_batch_autotune(mppi_batch *b, int32_t trials, void *stream, int
 /* enable != 0: replay the step from a HIP graph (the default); 0: launch. */
 mppi_status mppi_batch_set_graph(mppi_batch *b, int enable);
 
+/* Kernel timing of batched steps: while enabled, steps launch their three
+ * kernels directly (not from the graph; the kernels are the same) with HIP
+ * events on the step's stream around the persistent rollout kernel and
+ * around the update kernel.  mppi_batch_timing_read waits for the recorded
+ * steps, returns the summed milliseconds and the step count, and clears the
+ * records.  At most 4096 steps are kept. */
+mppi_status mppi_batch_timing_enable(mppi_batch *b, int enable);
+mppi_status mppi_batch_timing_read(mppi_batch *b, double *rollout_ms, double *update_ms, int32_t *n_steps);
+
 /* Device pointers of controller i's intermediate results (see mppi_debug_ptrs). */
 mppi_status mppi_batch_debug_view(const mppi_batch *b, int32_t i, mppi_debug_ptrs *out);
 

@@ -102,6 +102,10 @@ def lib():
         L.mppi_batch_set_graph.restype = ctypes.c_int
         L.mppi_batch_debug_view.argtypes = [V, I32, P(DebugPtrs)]
         L.mppi_batch_debug_view.restype = ctypes.c_int
+        L.mppi_batch_timing_enable.argtypes = [V, ctypes.c_int]
+        L.mppi_batch_timing_enable.restype = I32
+        L.mppi_batch_timing_read.argtypes = [V, P(ctypes.c_double), P(ctypes.c_double), P(I32)]
+        L.mppi_batch_timing_read.restype = I32
         L.mppi_batch_destroy.argtypes = [V]
         L.mppi_batch_destroy.restype = ctypes.c_int
         _lib = L
@@ -364,6 +368,16 @@ class Batch:
 
     def set_graph(self, on: bool) -> None:
         check(lib().mppi_batch_set_graph(self._h, 1 if on else 0))
+
+    def timing_enable(self, on: bool = True) -> None:
+        """While on, steps launch directly (no graph) with events around the kernels."""
+        check(lib().mppi_batch_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self) -> tuple[float, float, int]:
+        """(summed rollout-kernel ms, summed update-kernel ms, steps) since enable/read."""
+        r, u, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        check(lib().mppi_batch_timing_read(self._h, ctypes.byref(r), ctypes.byref(u), ctypes.byref(n)))
+        return r.value, u.value, n.value
 
     def debug(self, i: int) -> dict:
         torch = _torch()

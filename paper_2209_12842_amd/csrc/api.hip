@@ -669,6 +669,9 @@ struct mppi_batch {
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipEvent_t done;
+    bool timing;
+    std::vector<hipEvent_t> ev;  // 3 per timed step: start, after rollout, end
+    int n_timed;
 };
 
 namespace {
@@ -690,6 +693,7 @@ ramppi::BatchLaunch batch_launch_args(const mppi_batch* b) {
 }
 
 void batch_release(mppi_batch* b) {
+    for (hipEvent_t ev : b->ev) (void)hipEventDestroy(ev);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -789,6 +793,8 @@ mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* cons
     b->graph = nullptr;
     b->exec = nullptr;
     b->done = nullptr;
+    b->timing = false;
+    b->n_timed = 0;
     hipError_t e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = ramppi::batch_rollout_occupancy(&b->wg_max, bl.lds_rollout);
     if (e == hipSuccess)
@@ -892,7 +898,14 @@ mppi_status mppi_batch_step(mppi_batch* b, const float* x0_host, const uint32_t*
         for (int j = 0; j < 4; ++j) b->in_host[i].x0[j] = x0_host[4 * i + j];
         b->in_host[i].step_idx = step_idx_host[i];
     }
-    e = batch_launch(b, s, b->use_graph);
+    if (b->timing && b->n_timed < kMaxTimedSteps) {
+        hipEvent_t* e3 = &b->ev[3 * (size_t)b->n_timed];
+        e = ramppi::launch_batch(batch_launch_args(b), s, e3[0], e3[1]);
+        if (e == hipSuccess) e = hipEventRecord(e3[2], s);
+        if (e == hipSuccess) b->n_timed++;
+    } else {
+        e = batch_launch(b, s, b->use_graph);
+    }
     if (e == hipSuccess) e = hipEventRecord(b->done, s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     b->pending = true;
@@ -907,6 +920,41 @@ mppi_status mppi_batch_step(mppi_batch* b, const float* x0_host, const uint32_t*
 mppi_status mppi_batch_set_graph(mppi_batch* b, int enable) {
     if (!b) return fail(MPPI_EINVAL, "batch is NULL");
     b->use_graph = enable != 0;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_timing_enable(mppi_batch* b, int enable) {
+    if (!b) return fail(MPPI_EINVAL, "batch is NULL");
+    if (enable && b->ev.empty()) {
+        b->ev.resize(3 * (size_t)kMaxTimedSteps, nullptr);
+        for (auto& ev : b->ev) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+    }
+    b->timing = enable != 0;
+    b->n_timed = 0;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_timing_read(mppi_batch* b, double* rollout_ms, double* update_ms, int32_t* n_steps) {
+    if (!b || !rollout_ms || !update_ms || !n_steps) return fail(MPPI_EINVAL, "NULL argument");
+    double r = 0.0, u = 0.0;
+    for (int i = 0; i < b->n_timed; ++i) {
+        hipEvent_t* e3 = &b->ev[3 * (size_t)i];
+        hipError_t e = hipEventSynchronize(e3[2]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float x = 0.0f, y = 0.0f;
+        e = hipEventElapsedTime(&x, e3[0], e3[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&y, e3[1], e3[2]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        r += x;
+        u += y;
+    }
+    *rollout_ms = r;
+    *update_ms = u;
+    *n_steps = b->n_timed;
+    b->n_timed = 0;
     return MPPI_OK;
 }
 

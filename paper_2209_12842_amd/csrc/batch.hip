@@ -95,10 +95,12 @@ __global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict
                 b.w_hat, bush, red, &is_last);
 }
 
-hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream) {
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
     hipLaunchKernelGGL(k_batch_prep, dim3(L.n_ctl), dim3(256), 0, stream, L.ctls, L.inputs);
+    if (ev_start) (void)hipEventRecord(ev_start, stream);
     hipLaunchKernelGGL(k_batch_rollout, dim3(L.grid_rollout), dim3(256), L.lds_rollout, stream, L.ctls, L.items,
                        L.n_items, L.queue);
+    if (ev_mid) (void)hipEventRecord(ev_mid, stream);
     hipLaunchKernelGGL(k_batch_update, dim3(L.n_uitems), dim3(256), L.lds_update, stream, L.ctls, L.uitems);
     return hipGetLastError();
 }

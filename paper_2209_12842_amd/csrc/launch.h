@@ -66,7 +66,8 @@ struct BatchLaunch {
     size_t lds_rollout, lds_update;
 };
 
-hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream);
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_start = nullptr,
+                        hipEvent_t ev_mid = nullptr);
 hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout);
 
 // Buffers of the gradient of the free energy (see grad.hip).
