@@ -43,6 +43,13 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool finite(float v) { return std::isfinite(v); }
 
+// Dynamic LDS of the rollout kernel: controls, risk costs, tail slots and
+// means of the workgroup's samples, then the obstacle table in groups of 64.
+size_t rollout_lds_bytes(int spb, const mppi_params* p) {
+    if ((int64_t)spb * p->T > (1 << 24)) return SIZE_MAX;  // far beyond any LDS
+    return 4 * (size_t)ramppi::rollout_otab_offset(spb, p->T, p->M) + 16 * 64 * (size_t)ramppi::rollout_n_grp(p->n_obs);
+}
+
 // Launch geometry derived from the sizes.
 struct Geometry {
     int spb, block, n_nom_wg, G;
@@ -55,7 +62,7 @@ Geometry geometry(const mppi_params* p) {
     g.block = (g.spb * p->M + 63) / 64 * 64;
     g.n_nom_wg = (p->K + g.block - 1) / g.block;
     g.G = (p->K + kPartBlock - 1) / kPartBlock;
-    g.lds_rollout = 8 * (size_t)g.spb * p->T + 4 * (2 * (size_t)g.spb * p->M + g.spb);
+    g.lds_rollout = rollout_lds_bytes(g.spb, p);
     g.lds_update = ramppi::update_lds_bytes(p->T, g.G);
     return g;
 }
@@ -587,7 +594,7 @@ Geometry batch_geometry(const mppi_params* p) {
     g.spb = p->M >= kBatchBlock ? 1 : kBatchBlock / p->M;
     g.block = kBatchBlock;
     g.n_nom_wg = (p->K + kBatchBlock - 1) / kBatchBlock;
-    g.lds_rollout = 8 * (size_t)g.spb * p->T + 4 * (2 * (size_t)g.spb * p->M + g.spb);
+    g.lds_rollout = rollout_lds_bytes(g.spb, p);
     return g;
 }
 

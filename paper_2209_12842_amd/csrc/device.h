@@ -11,6 +11,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <climits>
 #include <stdint.h>
 
 namespace ramppi {
@@ -163,15 +165,23 @@ struct __attribute__((aligned(128))) ObstacleOct {
     float4 o[8];
 };
 
-// Number of obstacle discs strictly containing the point (Eq. 22 summed over
-// obstacles).  tab[i] = (-2 cx, -2 cy, r^2 - cx^2 - cy^2, 0) in the local
-// frame, so the point p is inside disc i iff |p|^2 + tab.x px + tab.y py <
-// tab.z.  The table is read with wave-uniform addresses (scalar loads into
-// SGPRs); per obstacle the test is two FMAs and one compare whose lane mask is
-// OR-ed into a wave-wide hit mask, and only a group of discs that some lane
-// of the wave is inside is counted lane by lane (from the sign of the same
+// Obstacle table entry i, in the frame of the start position (cx, cy relative
+// to x0): (-2 cx, -2 cy, r^2 - cx^2 - cy^2, q) with
+// q = (1 + 2^-16) r^2 + 2^-15 (cx^2 + cy^2), the squared reach of the
+// broad-phase test below.  Padding entries are (0, 0, -inf, -inf).
+//
+// Exact test (Eq. 22): the point p is inside disc i iff
+// |p|^2 + tab.x px + tab.y py < tab.z, evaluated as two FMAs on
+// rho = |p|^2 and one compare.
+
+// Number of obstacle discs strictly containing the point, brute force over
+// the table (used where a wave's points are spread out: one lane per sample).
+// The table is read with wave-uniform addresses (scalar loads into SGPRs);
+// per obstacle the test is two FMAs and one compare whose lane mask is OR-ed
+// into a wave-wide hit mask, and only a group of discs that some lane of the
+// wave is inside is counted lane by lane (from the sign of the same
 // difference, so both paths take the same decision).  The table is padded to
-// a multiple of 8 entries that no point can hit (tab.z = -inf).
+// a multiple of 8 entries that no point can hit.
 __device__ __forceinline__ int obstacle_hits(const ObstacleOct* __restrict__ tab, int n_oct, float px, float py) {
     const float rho = __fmaf_rn(px, px, py * py);
     int cnt = 0;
@@ -187,6 +197,82 @@ __device__ __forceinline__ int obstacle_hits(const ObstacleOct* __restrict__ tab
         if (hit) {
 #pragma unroll
             for (int j = 0; j < 8; ++j) cnt += (int)(__float_as_uint(s[j] - g.o[j].z) >> 31);
+        }
+    }
+    return cnt;
+}
+
+// Wave-wide minimum and maximum of a float over all 64 lanes (every lane
+// active), on order-preserving integer keys: the key of x flips the magnitude
+// bits of negative values, so signed-integer order equals float order (NaN
+// excepted).  Rows of 16 lanes reduce with DPP lane permutations, the four
+// row results are read into SGPRs and combined on the scalar unit.
+__device__ __forceinline__ int f32_key(float x) {
+    const int i = __float_as_int(x);
+    return i ^ (int)((uint32_t)(i >> 31) >> 1);
+}
+
+__device__ __forceinline__ float key_f32(int k) { return __int_as_float(k ^ (int)((uint32_t)(k >> 31) >> 1)); }
+
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i32(int v, int old) {
+    return __builtin_amdgcn_update_dpp(old, v, kCtrl, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ int wave_min_key(int v) {
+    v = min(v, dpp_i32<0xB1>(v, INT_MAX));   // quad_perm [1,0,3,2]
+    v = min(v, dpp_i32<0x4E>(v, INT_MAX));   // quad_perm [2,3,0,1]
+    v = min(v, dpp_i32<0x141>(v, INT_MAX));  // row_half_mirror
+    v = min(v, dpp_i32<0x140>(v, INT_MAX));  // row_mirror
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+__device__ __forceinline__ int wave_max_key(int v) {
+    v = max(v, dpp_i32<0xB1>(v, INT_MIN));
+    v = max(v, dpp_i32<0x4E>(v, INT_MIN));
+    v = max(v, dpp_i32<0x141>(v, INT_MIN));
+    v = max(v, dpp_i32<0x140>(v, INT_MIN));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+__device__ __forceinline__ float lane_f32(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Number of obstacle discs strictly containing the point, for a wave whose
+// points lie close together (the M draws of one sample).  Broad phase: the
+// wave's bounding box [x0, x1] x [y0, y1] against every disc, lane j testing
+// entry 64 g + j of the table staged in LDS (otab, n_grp groups of 64):
+// d2 = squared distance from the disc centre to the box, candidate iff
+// d2 < q + 2^-15 P^2, where P^2 = max(|x0|, |x1|)^2 + max(|y0|, |y1|)^2 bounds
+// |p|^2 over the box.  The margin exceeds the rounding error of both this
+// test and the exact test by more than twenty times (each is a few units in
+// the last place of r^2 + |c|^2 + |p|^2), so a disc that is not a candidate
+// fails the exact test in every lane.  Narrow phase: the exact test of the
+// candidates, their entries broadcast from lane j.  Every lane of the wave
+// must be active.
+__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float px, float py) {
+    const int kx = f32_key(px), ky = f32_key(py);
+    const float x0 = key_f32(wave_min_key(kx)), x1 = key_f32(wave_max_key(kx));
+    const float y0 = key_f32(wave_min_key(ky)), y1 = key_f32(wave_max_key(ky));
+    const float ax = fmaxf(fabsf(x0), fabsf(x1)), ay = fmaxf(fabsf(y0), fabsf(y1));
+    const float p2 = 3.0517578125e-05f * __fmaf_rn(ax, ax, ay * ay);  // 2^-15 P^2
+    const float rho = __fmaf_rn(px, px, py * py);
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+    for (int g = 0; g < n_grp; ++g) {
+        const float4 e = otab[g * 64 + lane];
+        const float cx = -0.5f * e.x, cy = -0.5f * e.y;
+        const float dx = fmaxf(fmaxf(x0 - cx, cx - x1), 0.0f);
+        const float dy = fmaxf(fmaxf(y0 - cy, cy - y1), 0.0f);
+        uint64_t cand = __builtin_amdgcn_ballot_w64(__fmaf_rn(dx, dx, dy * dy) < e.w + p2);
+        while (cand) {
+            const int j = __builtin_ctzll(cand);
+            cand &= cand - 1;
+            const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
+            cnt += (__fmaf_rn(a, px, __fmaf_rn(b, py, rho)) < z) ? 1 : 0;
         }
     }
     return cnt;

@@ -23,9 +23,11 @@ __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs,
         const float4 o = obs[i];  // cx, cy, r, unused
         const float cx = o.x - fx;
         const float cy = o.y - fy;
-        return make_float4(-2.0f * cx, -2.0f * cy, __fmaf_rn(o.z, o.z, -__fmaf_rn(cx, cx, cy * cy)), 0.0f);
+        const float c2 = __fmaf_rn(cx, cx, cy * cy);
+        const float q = __fmaf_rn(1.0000152587890625f * o.z, o.z, 3.0517578125e-05f * c2);
+        return make_float4(-2.0f * cx, -2.0f * cy, __fmaf_rn(o.z, o.z, -c2), q);
     }
-    return make_float4(0.0f, 0.0f, -__builtin_inff(), 0.0f);
+    return make_float4(0.0f, 0.0f, -__builtin_inff(), -__builtin_inff());
 }
 
 // LDS layout of k_rollout (dynamic shared memory, in this order):
@@ -33,6 +35,14 @@ __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs,
 //   float  vals[spb * M]  risk costs of the WG's samples
 //   float  tail[spb * M]  tail slots (descending)
 //   float  means[spb]     mean risk cost per sample (risk scaling)
+//   float4 otab[64 n_grp] the obstacle table, padded to groups of 64 entries
+//                         (16-byte aligned; n_grp = ceil(n_obs / 64))
+// rollout_lds_floats gives the offset of otab and the total, in floats.
+__host__ __device__ __forceinline__ int rollout_otab_offset(int spb, int T, int M) {
+    return (2 * spb * T + 2 * spb * M + spb + 3) & ~3;
+}
+
+__host__ __device__ __forceinline__ int rollout_n_grp(int n_obs) { return (n_obs + 63) >> 6; }
 // Scal, Max and Average of Algorithm 1 for the spb samples of a workgroup.
 // vals holds the raw risk costs (thread tid owns slot tid for tid < spb * M);
 // returns the CVaR in the m == 0 lane of each sample.
@@ -111,6 +121,14 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
     // ---- disturbed rollouts: one lane per (sample, draw) ----
     const int wg = item - c.n_nom_wg;
     const int spb = c.spb, M = c.M, T = c.T;
+    const int n_grp = rollout_n_grp(c.n_obs);
+    float4* otab = reinterpret_cast<float4*>(reinterpret_cast<float*>(smem) + rollout_otab_offset(spb, T, M));
+    {
+        const float4* tab4 = reinterpret_cast<const float4*>(tab);
+        const int n_pad = n_oct * 8;
+        for (int i = tid; i < n_grp * 64; i += blockDim.x)
+            otab[i] = (i < n_pad) ? tab4[i] : make_float4(0.0f, 0.0f, -__builtin_inff(), -__builtin_inff());
+    }
     for (int idx = tid; idx < spb * T; idx += blockDim.x) {
         const int sl = idx / T;
         const int t = idx - sl * T;
@@ -129,14 +147,17 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
     const int k = wg * spb + sl;
     const bool active = (sl < spb) && (k < c.K);
     float L = 0.0f;
-    if (active) {
-        const float2* ck = ctl + sl * T;
+    {
+        // every lane runs a rollout (the obstacle test works on whole waves);
+        // lanes past the workgroup's last sample repeat its controls, and the
+        // results of inactive lanes are dropped
+        const float2* ck = ctl + min(sl, spb - 1) * T;
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f;
         int cnt = 0;
         for (int t = 0; t < T; ++t) {
             acc += smooth_cost(c, s);
-            cnt += obstacle_hits(tab, n_oct, s.x, s.y);
+            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y);
             if (t + 1 < T) {  // the last draw cannot reach the risk cost
                 const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
                 const float4 w = disturbance<kNoise>(c, r);
@@ -148,8 +169,10 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
                 s.v += w.w;
             }
         }
-        L = __fmaf_rn(c.c_obs, (float)cnt, acc);
-        if (c.debug) L_out[(size_t)k * M + m] = L;
+        if (active) {
+            L = __fmaf_rn(c.c_obs, (float)cnt, acc);
+            if (c.debug) L_out[(size_t)k * M + m] = L;
+        }
     }
     if (sl < spb) {
         vals[tid] = L;

@@ -254,6 +254,33 @@ def test_edge_shapes(kw):
     _run(p, obs, x0, V0, 1)
 
 
+def _dense_obstacles(n, seed, x0, r=(0.1, 0.5)):
+    """n discs scattered around x0 over a square of half side
+    max(25, 25 sqrt(n / 300)) m (the first one on the start heading, 4 m
+    ahead, radius 0.6 m), so that many rollouts end up inside discs."""
+    half = max(25.0, 25.0 * np.sqrt(n / 300.0))
+    rng = np.random.default_rng(seed)
+    c = np.asarray(x0[:2], dtype=np.float64) + rng.uniform(-half, half, size=(n, 2))
+    rr = rng.uniform(r[0], r[1], size=n)
+    c[0] = np.asarray(x0[:2], dtype=np.float64) + 4.0 * np.array([np.cos(x0[2]), np.sin(x0[2])])
+    rr[0] = 0.6
+    return np.column_stack([c, rr]).astype(np.float32)
+
+
+@pytest.mark.parametrize("n_obs,M", [(1, 64), (63, 64), (64, 48), (65, 16), (300, 64), (1024, 128), (200, 300)])
+def test_dense_obstacle_fields(n_obs, M):
+    # obstacle counts when many rollouts pass through discs: every group size
+    # of the obstacle table (1, 63, 64, 65, 300, 1024 entries) and waves that
+    # hold one sample (M >= 64) or several (M = 16, 48)
+    p, _, x0, _ = _world("c1", K=256, M=M, T=30, lam=50.0)
+    obs = _dense_obstacles(n_obs, 11 + n_obs, x0)
+    V0 = W.random_V(p["T"], 7, scale=(1.0, 0.2))
+    g, o, rep = _run(p, obs, x0, V0, 2, strict=False)
+    hits = float((o["L"] >= float(np.float32(p["c_obs"]))).mean())
+    _log("  fraction of disturbed rollouts with a collision: %.3f" % hits)
+    assert hits > 0.02
+
+
 def test_shift_and_first_command():
     p, obs, x0, V0 = _world("c1", shift=True)
     g, o, rep = _run(p, obs, x0, V0, 0, shift=True)
