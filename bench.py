@@ -7,9 +7,12 @@ the first command read back every step and a host FP64 plant closing the
 loop.  Synthetic seeded inputs.  One JSON line on stdout:
 
   value        rollout-steps/s (K M T per step) over the timed steps
-  roofline     the rollout kernel: model FP32 FLOPs per launch / its average
-               HIP-event duration on the step's stream, against the FP32
-               vector peak
+  roofline     the rollout kernel: the FP32 FLOPs it executes per launch
+               (with the broad-phase candidates counted on the device over
+               the timed steps) / its average HIP-event duration on the
+               step's stream, against the FP32 vector peak; the
+               brute-force-equivalent rate (every obstacle tested at every
+               state) is given beside it
   cpu_baseline the FP64 oracle on a bounded sample of the same workload,
                timed on this host's cores
 
@@ -47,10 +50,34 @@ PEAK_HBM_GBS = 8000.0
 
 
 def model_flops(p: dict, n_obs: int) -> float:
-    """FP32 FLOPs of one rollout launch: 80 + 7 n_obs per disturbed state
-    step (K M T of them) and 60 + 7 n_obs per nominal state step (K T)."""
+    """Brute-force-equivalent FP32 FLOPs of one rollout launch: 80 + 7 n_obs
+    per disturbed state step (K M T of them) and 60 + 7 n_obs per nominal
+    state step (K T), every obstacle tested at every state."""
     K, T, M = p["K"], p["T"], p["M"]
     return K * M * T * (80.0 + 7.0 * n_obs) + K * T * (60.0 + 7.0 * n_obs)
+
+
+def rollout_waves(p: dict, block: int | None = None) -> int:
+    """Waves of one rollout launch (nominal and disturbed workgroups)."""
+    K, M = p["K"], p["M"]
+    spb = 1 if M >= 256 else 256 // M
+    if block is None:
+        block = (spb * M + 63) // 64 * 64
+    n_nom = (K + block - 1) // block
+    n_dist = (K + spb - 1) // spb
+    return (n_nom + n_dist) * (block // 64)
+
+
+def executed_flops(p: dict, n_obs: int, candidates: float, block: int | None = None) -> float:
+    """FP32 FLOPs the culled rollout kernel executes in one launch (FMA = 2):
+    80 per disturbed and 60 per nominal state step for dynamics, noise and
+    the smooth costs; per wave, state step and table slot (groups of 64) 17
+    for the broad-phase box test; 5 per lane for each exact test of a
+    broad-phase candidate (`candidates` counted on the device, per wave)."""
+    K, T, M = p["K"], p["T"], p["M"]
+    n_grp = (n_obs + 63) // 64
+    return (80.0 * K * M * T + 60.0 * K * T + 17.0 * 64 * n_grp * T * rollout_waves(p, block)
+            + 5.0 * 64 * candidates)
 
 
 def model_bytes(p: dict, n_obs: int) -> float:
@@ -151,14 +178,16 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     roll_ms, upd_ms, n_timed = ctl.timing_read()
+    cand = ctl.timing_candidates() / max(n_timed, 1)
     ctl.timing_enable(False)
     assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(np.asarray(x)))
 
     steps_per_call = K * M * T
     value = steps_per_call * args.steps / elapsed
     roll_avg_s = roll_ms / max(n_timed, 1) * 1e-3
-    flops = model_flops(p, n_obs)
+    flops = executed_flops(p, n_obs, cand)
     achieved_tf = flops / roll_avg_s / 1e12
+    brute_tf = model_flops(p, n_obs) / roll_avg_s / 1e12
     out = {
         "metric": "rollout-steps/s (K*M*T per mppi_step), receding-horizon loop",
         "value": value,
@@ -179,7 +208,9 @@ def main():
         "kernel_ms": {"rollout": roll_avg_s * 1e3, "update": upd_ms / max(n_timed, 1)},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_rollout", "model_flops_per_launch": flops},
+                     "kernel": "k_rollout", "executed_flops_per_launch": flops,
+                     "broad_phase_candidates_per_launch": cand,
+                     "brute_force_equivalent_tflops": brute_tf},
     }
     if args.calibrate_copy > 0:
         n = args.calibrate_copy << 20
@@ -203,7 +234,7 @@ def run_batch(args, R, torch):
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     work = sum(w["params"]["K"] * w["params"]["M"] * w["params"]["T"] for w in ws)
-    flops = sum(model_flops(w["params"], len(w["obstacles"])) for w in ws)
+    brute = sum(model_flops(w["params"], len(w["obstacles"])) for w in ws)
     dt32 = np.array([float(np.float32(w["params"]["dt"])) for w in ws])
     wb32 = np.array([float(np.float32(w["params"]["wheelbase"])) for w in ws])
     sw = np.stack([np.sqrt(np.float32(w["params"]["sigma_w"]).astype(np.float64)) for w in ws])
@@ -271,11 +302,14 @@ def run_batch(args, R, torch):
     for j in range(n_k):
         b.step(x, n_total + j, want_u0=False)
     roll_ms, upd_ms, n_timed = b.timing_read()
+    cand = b.timing_candidates() / max(n_timed, 1)
     b.timing_enable(False)
     b.close()
 
     roll_avg_s = roll_ms / max(n_timed, 1) * 1e-3
+    flops = sum(executed_flops(w["params"], len(w["obstacles"]), 0.0, block=256) for w in ws) + 5.0 * 64 * cand
     achieved_tf = flops / roll_avg_s / 1e12
+    brute_tf = brute / roll_avg_s / 1e12
     value = work * args.steps / elapsed
     seq_value = work * args.steps / seq_elapsed
     out = {
@@ -296,7 +330,8 @@ def run_batch(args, R, torch):
                       "measured_over": "%d direct launches after the timed steps" % n_timed},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_batch_rollout",
-                     "model_flops_per_launch": flops},
+                     "executed_flops_per_launch": flops, "broad_phase_candidates_per_launch": cand,
+                     "brute_force_equivalent_tflops": brute_tf},
     }
     print(json.dumps(out), flush=True)
 
@@ -331,30 +366,43 @@ def run_grad(args, R, torch):
     Vs = V.clone()
     s_ms = timed(lambda j: ctl.step(x0, Vs, j, want_u0=False), args.steps)
 
-    # equal wall time: plain steps against (step, gradient, correction) rounds
-    # from V = 0 at the start state, each round on fresh noise; both final
-    # sequences are scored by the mean free energy over 16 held-out call
-    # indices (lower is better)
+    # equal wall time: from V = 0 at the start state, plain steps against
+    # rounds of (step, gradient, backtracking correction), each on fresh
+    # noise, for the same wall-clock budget; both final sequences are scored
+    # by the mean free energy over 16 held-out call indices (lower is better)
     def score(Vf):
         js = [ctl.free_energy(x0, Vf, 1_000_000 + i)[0] for i in range(16)]
         return float(torch.stack(js).mean().item())
 
-    budget_rounds = 20
-    n_plain = int(round(budget_rounds * (s_ms + g_ms) / s_ms))
-    tau = 0.05
+    def grad_round(Vg, j):
+        ctl.step(x0, Vg, 10_000 + j, want_u0=False)
+        J0, g = ctl.free_energy(x0, Vg, 20_000 + j)
+        gn = g / g.abs().max().clamp_min(1e-30)
+        for tau in (0.3, 0.1, 0.03, 0.01):  # Armijo-style backtracking on the gradient's own noise
+            Vt = (Vg - tau * gn).contiguous()
+            if ctl.free_energy(x0, Vt, 20_000 + j)[0].item() < J0.item():
+                Vg.copy_(Vt)
+                break
+
+    Vw = ctl.new_V()
+    for j in range(3):  # warm-up of the torch elementwise kernels used above
+        grad_round(Vw, 90_000 + j)
+    budget_s = 0.25
     Vp = ctl.new_V()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in range(n_plain):
-        ctl.step(x0, Vp, 10_000 + j, want_u0=False)
-    torch.cuda.synchronize()
+    n_plain = 0
+    while time.perf_counter() - t0 < budget_s:
+        ctl.step(x0, Vp, 10_000 + n_plain, want_u0=True)
+        n_plain += 1
     t_plain = time.perf_counter() - t0
     Vg = ctl.new_V()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in range(budget_rounds):
-        ctl.step(x0, Vg, 10_000 + j, want_u0=False)
-        _, g = ctl.free_energy(x0, Vg, 20_000 + j)
-        Vg -= tau * g / g.abs().max().clamp_min(1e-30)
+    n_grad = 0
+    while time.perf_counter() - t0 < budget_s:
+        grad_round(Vg, n_grad)
+        n_grad += 1
     torch.cuda.synchronize()
     t_grad = time.perf_counter() - t0
     out = {
@@ -365,8 +413,9 @@ def run_grad(args, R, torch):
         "config": {"workload": "%s: K=%d T=%d M=%d n_obs=%d lambda=%g, mppi_grad (forward + adjoint)"
                                % (name, K, T, M, len(obs), p["lam"]), "parallelism": "single GPU"},
         "plain_step_ms": s_ms, "gradient_over_step": g_ms / s_ms,
-        "equal_wall_time": {"plain_steps": n_plain, "plain_s": t_plain, "grad_rounds": budget_rounds,
-                            "grad_s": t_grad, "tau": tau, "J_plain": score(Vp), "J_grad_corrected": score(Vg)},
+        "equal_wall_time": {"budget_s": budget_s, "plain_steps": n_plain, "plain_s": t_plain,
+                            "grad_rounds": n_grad, "grad_s": t_grad, "J_plain": score(Vp),
+                            "J_grad_corrected": score(Vg)},
     }
     print(json.dumps(out), flush=True)
     ctl.close()

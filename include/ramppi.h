@@ -188,6 +188,13 @@ mppi_status mppi_debug_view(const mppi_handle *h, mppi_debug_ptrs *out);
 mppi_status mppi_timing_enable(mppi_handle *h, int enable);
 mppi_status mppi_timing_read(mppi_handle *h, double *rollout_ms, double *update_ms, int32_t *n_steps);
 
+/* Work counter of the rollout kernel's obstacle test: the number of
+ * (wave, state step, obstacle) candidates that passed the broad phase and
+ * were tested exactly, summed over the steps enqueued while timing was
+ * enabled, since the last call.  Waits for `stream`, then clears the
+ * counter. */
+mppi_status mppi_timing_candidates(mppi_handle *h, void *stream, uint64_t *n_candidates);
+
 /* ---- Stage entry points (same device code as the fused step) ---- */
 
 /* Philox4x32-10 (Salmon et al. 2011) of n counters: ctr_dev n x 4 uint32,
@@ -259,6 +266,8 @@ mppi_status mppi_batch_set_graph(mppi_batch *b, int enable);
  * records.  At most 4096 steps are kept. */
 mppi_status mppi_batch_timing_enable(mppi_batch *b, int enable);
 mppi_status mppi_batch_timing_read(mppi_batch *b, double *rollout_ms, double *update_ms, int32_t *n_steps);
+/* As mppi_timing_candidates, over the batch's timed steps. */
+mppi_status mppi_batch_timing_candidates(mppi_batch *b, void *stream, uint64_t *n_candidates);
 
 /* Device pointers of controller i's intermediate results (see mppi_debug_ptrs). */
 mppi_status mppi_batch_debug_view(const mppi_batch *b, int32_t i, mppi_debug_ptrs *out);

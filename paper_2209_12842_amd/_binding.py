@@ -106,6 +106,10 @@ def lib():
         L.mppi_batch_timing_enable.restype = I32
         L.mppi_batch_timing_read.argtypes = [V, P(ctypes.c_double), P(ctypes.c_double), P(I32)]
         L.mppi_batch_timing_read.restype = I32
+        L.mppi_timing_candidates.argtypes = [V, V, P(U64)]
+        L.mppi_timing_candidates.restype = I32
+        L.mppi_batch_timing_candidates.argtypes = [V, V, P(U64)]
+        L.mppi_batch_timing_candidates.restype = I32
         L.mppi_batch_destroy.argtypes = [V]
         L.mppi_batch_destroy.restype = ctypes.c_int
         _lib = L
@@ -258,6 +262,12 @@ class Controller:
         check(lib().mppi_timing_read(self._h, ctypes.byref(r), ctypes.byref(u), ctypes.byref(n)))
         return r.value, u.value, n.value
 
+    def timing_candidates(self) -> int:
+        """Broad-phase obstacle candidates of the steps timed since the last call."""
+        n = ctypes.c_uint64()
+        check(lib().mppi_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(n)))
+        return n.value
+
     def close(self) -> None:
         if self._h:
             lib().mppi_destroy(self._h)
@@ -378,6 +388,13 @@ class Batch:
         r, u, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
         check(lib().mppi_batch_timing_read(self._h, ctypes.byref(r), ctypes.byref(u), ctypes.byref(n)))
         return r.value, u.value, n.value
+
+    def timing_candidates(self) -> int:
+        """Broad-phase obstacle candidates of the steps timed since the last call."""
+        n = ctypes.c_uint64()
+        check(lib().mppi_batch_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)),
+                                                 ctypes.byref(n)))
+        return n.value
 
     def debug(self, i: int) -> dict:
         torch = _torch()

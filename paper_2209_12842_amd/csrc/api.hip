@@ -81,7 +81,7 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, counter;
+    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work;
     // gradient buffers (MPPI_F_GRAD)
     size_t ranks, tail_idx, act_list, n_act, J, states, rows, rpart, gcounter;
     int R, stride, n_lane_blocks;
@@ -103,6 +103,7 @@ Layout layout(const mppi_params* p) {
     l.part = o;    o += align_up(4 * (size_t)g.G * (2 + 2 * (size_t)p->T));
     l.u0 = o;      o += align_up(8);
     l.counter = o; o += align_up(4);
+    l.work = o;    o += align_up(8 * (size_t)ramppi::kWorkSlots);
     l.ranks = l.tail_idx = l.act_list = l.n_act = l.J = l.states = l.rows = l.rpart = l.gcounter = 0;
     l.R = l.stride = l.n_lane_blocks = 0;
     if (p->flags & MPPI_F_GRAD) {
@@ -246,7 +247,21 @@ ramppi::StepBuffers step_buffers(const mppi_handle* h, float* V_dev) {
     bufs.u0 = reinterpret_cast<float*>(h->ws + h->l.u0);
     bufs.counter = reinterpret_cast<unsigned*>(h->ws + h->l.counter);
     bufs.u0_host = nullptr;
+    bufs.work = nullptr;
     return bufs;
+}
+
+// Sums and clears kWorkSlots device counters (waits for `s`).
+hipError_t read_work(unsigned long long* dev, hipStream_t s, uint64_t* out) {
+    unsigned long long host[ramppi::kWorkSlots];
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof host, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemsetAsync(dev, 0, sizeof host, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    uint64_t sum = 0;
+    for (int i = 0; i < ramppi::kWorkSlots; ++i) sum += host[i];
+    *out = sum;
+    return e;
 }
 
 }  // namespace
@@ -369,6 +384,7 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     }
     e = hipMemcpyAsync(h->ws + l.obs, staged.data(), 16 * (size_t)p->n_obs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.counter, 0, 4, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.work, 0, 8 * (size_t)ramppi::kWorkSlots, s);
     if (e == hipSuccess && (p->flags & MPPI_F_GRAD)) e = hipMemsetAsync(h->ws + l.gcounter, 0, 4, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -415,6 +431,7 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         ev_mid = e3[1];
         ev_end = e3[2];
     }
+    if (h->timing) bufs.work = reinterpret_cast<unsigned long long*>(h->ws + h->l.work);
     hipError_t e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_update, s, ev_start, ev_mid);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     if (ev_end) {
@@ -527,6 +544,14 @@ mppi_status mppi_timing_read(mppi_handle* h, double* rollout_ms, double* update_
     return MPPI_OK;
 }
 
+mppi_status mppi_timing_candidates(mppi_handle* h, void* stream, uint64_t* n_candidates) {
+    if (!h || !n_candidates) return fail(MPPI_EINVAL, "NULL argument");
+    const hipError_t e = read_work(reinterpret_cast<unsigned long long*>(h->ws + h->l.work),
+                                   static_cast<hipStream_t>(stream), n_candidates);
+    if (e != hipSuccess) return hip_fail(e, "candidate counters");
+    return MPPI_OK;
+}
+
 mppi_status mppi_philox(uint64_t seed, const uint32_t* ctr_dev, uint32_t* out_dev, int64_t n, void* stream) {
     if (n < 0) return fail(MPPI_EINVAL, "n < 0");
     if (n == 0) return MPPI_OK;
@@ -601,7 +626,7 @@ Geometry batch_geometry(const mppi_params* p) {
 int n_dist_wg(const mppi_params* p, const Geometry& g) { return (p->K + g.spb - 1) / g.spb; }
 
 struct BatchLayout {
-    size_t ctls, items, uitems, queue, vbackup;
+    size_t ctls, items, uitems, queue, vbackup, work;
     std::vector<size_t> ctl_base;
     size_t total;
     int n_items, n_uitems;
@@ -647,6 +672,7 @@ BatchLayout batch_layout(int32_t n, const mppi_params* p) {
     bl.items = o;   o += align_up(8 * (size_t)bl.n_items);
     bl.uitems = o;  o += align_up(8 * (size_t)bl.n_uitems);
     bl.queue = o;   o += align_up(8);
+    bl.work = o;    o += align_up(8 * (size_t)ramppi::kWorkSlots);
     bl.vbackup = o; o += vback;
     bl.ctl_base.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -690,6 +716,7 @@ ramppi::BatchLaunch batch_launch_args(const mppi_batch* b) {
     L.items = reinterpret_cast<const int2*>(b->ws + b->bl.items);
     L.uitems = reinterpret_cast<const int2*>(b->ws + b->bl.uitems);
     L.queue = reinterpret_cast<unsigned*>(b->ws + b->bl.queue);
+    L.work = nullptr;
     L.n_ctl = b->n;
     L.n_items = b->bl.n_items;
     L.n_uitems = b->bl.n_uitems;
@@ -880,6 +907,7 @@ mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* cons
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ws + bl.uitems, uitems.data(), 8 * uitems.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.queue, 0, 8, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.work, 0, 8 * (size_t)ramppi::kWorkSlots, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         batch_release(b);
@@ -907,7 +935,9 @@ mppi_status mppi_batch_step(mppi_batch* b, const float* x0_host, const uint32_t*
     }
     if (b->timing && b->n_timed < kMaxTimedSteps) {
         hipEvent_t* e3 = &b->ev[3 * (size_t)b->n_timed];
-        e = ramppi::launch_batch(batch_launch_args(b), s, e3[0], e3[1]);
+        ramppi::BatchLaunch L = batch_launch_args(b);
+        L.work = reinterpret_cast<unsigned long long*>(b->ws + b->bl.work);
+        e = ramppi::launch_batch(L, s, e3[0], e3[1]);
         if (e == hipSuccess) e = hipEventRecord(e3[2], s);
         if (e == hipSuccess) b->n_timed++;
     } else {
@@ -962,6 +992,14 @@ mppi_status mppi_batch_timing_read(mppi_batch* b, double* rollout_ms, double* up
     *update_ms = u;
     *n_steps = b->n_timed;
     b->n_timed = 0;
+    return MPPI_OK;
+}
+
+mppi_status mppi_batch_timing_candidates(mppi_batch* b, void* stream, uint64_t* n_candidates) {
+    if (!b || !n_candidates) return fail(MPPI_EINVAL, "NULL argument");
+    const hipError_t e = read_work(reinterpret_cast<unsigned long long*>(b->ws + b->bl.work),
+                                   static_cast<hipStream_t>(stream), n_candidates);
+    if (e != hipSuccess) return hip_fail(e, "candidate counters");
     return MPPI_OK;
 }
 

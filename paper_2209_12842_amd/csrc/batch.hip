@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(256) k_batch_prep(BatchCtl* __restrict__ ctls,
 
 __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restrict__ ctls,
                                                        const int2* __restrict__ items, int n_items,
-                                                       unsigned* queue) {
+                                                       unsigned* queue, unsigned long long* __restrict__ work) {
     extern __shared__ float2 bsmem[];
     __shared__ int item_sh;
     for (;;) {
@@ -67,11 +67,11 @@ __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restric
         const StepConst c = b.c;
         const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
         if (c.noise_kind == 1)
-            rollout_body<1>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem);
+            rollout_body<1>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
         else if (c.noise_kind == 2)
-            rollout_body<2>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem);
+            rollout_body<2>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
         else
-            rollout_body<0>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem);
+            rollout_body<0>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
         __syncthreads();  // LDS is reused by the next item
     }
     if (threadIdx.x == 0) {
@@ -99,7 +99,7 @@ hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_
     hipLaunchKernelGGL(k_batch_prep, dim3(L.n_ctl), dim3(256), 0, stream, L.ctls, L.inputs);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
     hipLaunchKernelGGL(k_batch_rollout, dim3(L.grid_rollout), dim3(256), L.lds_rollout, stream, L.ctls, L.items,
-                       L.n_items, L.queue);
+                       L.n_items, L.queue, L.work);
     if (ev_mid) (void)hipEventRecord(ev_mid, stream);
     hipLaunchKernelGGL(k_batch_update, dim3(L.n_uitems), dim3(256), L.lds_update, stream, L.ctls, L.uitems);
     return hipGetLastError();

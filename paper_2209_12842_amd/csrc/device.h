@@ -174,34 +174,6 @@ struct __attribute__((aligned(128))) ObstacleOct {
 // |p|^2 + tab.x px + tab.y py < tab.z, evaluated as two FMAs on
 // rho = |p|^2 and one compare.
 
-// Number of obstacle discs strictly containing the point, brute force over
-// the table (used where a wave's points are spread out: one lane per sample).
-// The table is read with wave-uniform addresses (scalar loads into SGPRs);
-// per obstacle the test is two FMAs and one compare whose lane mask is OR-ed
-// into a wave-wide hit mask, and only a group of discs that some lane of the
-// wave is inside is counted lane by lane (from the sign of the same
-// difference, so both paths take the same decision).  The table is padded to
-// a multiple of 8 entries that no point can hit.
-__device__ __forceinline__ int obstacle_hits(const ObstacleOct* __restrict__ tab, int n_oct, float px, float py) {
-    const float rho = __fmaf_rn(px, px, py * py);
-    int cnt = 0;
-    for (int i = 0; i < n_oct; ++i) {
-        const ObstacleOct g = tab[i];
-        float s[8];
-        uint64_t hit = 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            s[j] = __fmaf_rn(g.o[j].x, px, __fmaf_rn(g.o[j].y, py, rho));
-            hit |= __builtin_amdgcn_ballot_w64(s[j] < g.o[j].z);
-        }
-        if (hit) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) cnt += (int)(__float_as_uint(s[j] - g.o[j].z) >> 31);
-        }
-    }
-    return cnt;
-}
-
 // Wave-wide minimum and maximum of a float over all 64 lanes (every lane
 // active), on order-preserving integer keys: the key of x flips the magnitude
 // bits of negative values, so signed-integer order equals float order (NaN
@@ -252,8 +224,9 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
 // the last place of r^2 + |c|^2 + |p|^2), so a disc that is not a candidate
 // fails the exact test in every lane.  Narrow phase: the exact test of the
 // candidates, their entries broadcast from lane j.  Every lane of the wave
-// must be active.
-__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float px, float py) {
+// must be active.  n_cand counts the candidates (wave-uniform).
+__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float px, float py,
+                                                    int& n_cand) {
     const int kx = f32_key(px), ky = f32_key(py);
     const float x0 = key_f32(wave_min_key(kx)), x1 = key_f32(wave_max_key(kx));
     const float y0 = key_f32(wave_min_key(ky)), y1 = key_f32(wave_max_key(ky));
@@ -271,6 +244,7 @@ __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ o
         while (cand) {
             const int j = __builtin_ctzll(cand);
             cand &= cand - 1;
+            ++n_cand;
             const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
             cnt += (__fmaf_rn(a, px, __fmaf_rn(b, py, rho)) < z) ? 1 : 0;
         }

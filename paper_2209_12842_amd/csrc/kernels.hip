@@ -33,9 +33,9 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct
                                                   const float* __restrict__ V, float2* __restrict__ u_out,
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
                                                   float* __restrict__ L_out, int* __restrict__ ranks,
-                                                  int* __restrict__ tail_idx) {
+                                                  int* __restrict__ tail_idx, unsigned long long* __restrict__ work) {
     extern __shared__ float2 smem[];
-    rollout_body<kNoise>(c, tab, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx);
+    rollout_body<kNoise>(c, tab, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx, work);
 }
 
 __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
@@ -101,13 +101,13 @@ hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, s
     const dim3 grid(c.n_nom_wg + n_dist_wg);
     if (c.noise_kind == 1)
         hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
-                           ranks, tail_idx);
+                           ranks, tail_idx, b.work);
     else if (c.noise_kind == 2)
         hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
-                           ranks, tail_idx);
+                           ranks, tail_idx, b.work);
     else
         hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
-                           ranks, tail_idx);
+                           ranks, tail_idx, b.work);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct StepBuffers {
     unsigned* counter;  // chunks finished in the current update (0 between launches)
     float* u0;          // 2
     float* u0_host;     // 2 floats of mapped pinned host memory, or null
+    unsigned long long* work;  // kWorkSlots broad-phase candidate counters, or null
 };
 
 // One controller of a batch, in device memory: its step constants (the static
@@ -62,6 +63,7 @@ struct BatchLaunch {
     const int2* items;         // rollout items (controller, workgroup), in queue order
     const int2* uitems;        // update items (controller, chunk)
     unsigned* queue;           // 2 counters, zero between launches
+    unsigned long long* work;  // kWorkSlots broad-phase candidate counters, or null
     int n_ctl, n_items, n_uitems, grid_rollout;
     size_t lds_rollout, lds_update;
 };

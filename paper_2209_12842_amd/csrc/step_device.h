@@ -43,6 +43,10 @@ __host__ __device__ __forceinline__ int rollout_otab_offset(int spb, int T, int 
 }
 
 __host__ __device__ __forceinline__ int rollout_n_grp(int n_obs) { return (n_obs + 63) >> 6; }
+
+// Slots of the broad-phase candidate counters (wave w of item i adds to slot
+// (16 i + w) mod kWorkSlots, spreading the atomics).
+constexpr int kWorkSlots = 256;
 // Scal, Max and Average of Algorithm 1 for the spb samples of a workgroup.
 // vals holds the raw risk costs (thread tid owns slot tid for tid < spb * M);
 // returns the CVaR in the m == 0 lane of each sample.
@@ -85,26 +89,40 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
                                              const float* __restrict__ V, float2* __restrict__ u_out,
                                              float* __restrict__ S_out, float* __restrict__ cvar_out,
                                              float* __restrict__ L_out, int item, float2* smem,
-                                             int* __restrict__ ranks = nullptr, int* __restrict__ tail_idx = nullptr) {
+                                             int* __restrict__ ranks = nullptr, int* __restrict__ tail_idx = nullptr,
+                                             unsigned long long* __restrict__ work = nullptr) {
     float2* ctl = smem;
     float* vals = reinterpret_cast<float*>(ctl + (size_t)c.spb * c.T);
     float* tail = vals + c.spb * c.M;
     float* means = tail + c.spb * c.M;
     const int tid = threadIdx.x;
-    const int n_oct = (c.n_obs + 7) >> 3;
+    const int spb = c.spb, M = c.M, T = c.T;
+    const int n_grp = rollout_n_grp(c.n_obs);
+    float4* otab = reinterpret_cast<float4*>(reinterpret_cast<float*>(smem) + rollout_otab_offset(spb, T, M));
+    {
+        const float4* tab4 = reinterpret_cast<const float4*>(tab);
+        const int n_pad = ((c.n_obs + 7) >> 3) * 8;
+        for (int i = tid; i < n_grp * 64; i += blockDim.x)
+            otab[i] = (i < n_pad) ? tab4[i] : make_float4(0.0f, 0.0f, -__builtin_inff(), -__builtin_inff());
+    }
+    int n_cand = 0;  // broad-phase candidates of this wave (wave-uniform)
 
     if (item < c.n_nom_wg) {
-        // ---- nominal rollouts: one lane per sample ----
+        // ---- nominal rollouts: one lane per sample; lanes past K repeat
+        // the last sample (the obstacle test works on whole waves) and write
+        // nothing ----
+        __syncthreads();  // otab staged
         const int k = item * blockDim.x + tid;
-        if (k >= c.K) return;
+        const bool act = k < c.K;
+        const int kc = act ? k : c.K - 1;
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
-        for (int t = 0; t < c.T; ++t) {
-            const float2 u = sample_control(c, V, k, t);
-            u_out[(size_t)t * c.K + k] = u;
+        for (int t = 0; t < T; ++t) {
+            const float2 u = sample_control(c, V, kc, t);
+            if (act) u_out[(size_t)t * c.K + k] = u;
             acc += smooth_cost(c, s);
-            cnt += obstacle_hits(tab, n_oct, s.x, s.y);
+            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y, n_cand);
             if (c.use_ctrl) {
                 const float term = __fmaf_rn(V[2 * t] * c.inv_var0, u.x, V[2 * t + 1] * c.inv_var1 * u.y);
                 ctrl = __fmaf_rn(c.gamma, term, ctrl);
@@ -114,21 +132,14 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
         float S = __fmaf_rn(c.c_obs, (float)cnt, acc);
         if (c.use_ctrl) S += ctrl;
         if (c.use_term) S += terminal_cost(c, s);
-        S_out[k] = S;
+        if (act) S_out[k] = S;
+        if (work && (tid & 63) == 0)
+            atomicAdd(&work[(item * 16 + (tid >> 6)) & (kWorkSlots - 1)], (unsigned long long)n_cand);
         return;
     }
 
     // ---- disturbed rollouts: one lane per (sample, draw) ----
     const int wg = item - c.n_nom_wg;
-    const int spb = c.spb, M = c.M, T = c.T;
-    const int n_grp = rollout_n_grp(c.n_obs);
-    float4* otab = reinterpret_cast<float4*>(reinterpret_cast<float*>(smem) + rollout_otab_offset(spb, T, M));
-    {
-        const float4* tab4 = reinterpret_cast<const float4*>(tab);
-        const int n_pad = n_oct * 8;
-        for (int i = tid; i < n_grp * 64; i += blockDim.x)
-            otab[i] = (i < n_pad) ? tab4[i] : make_float4(0.0f, 0.0f, -__builtin_inff(), -__builtin_inff());
-    }
     for (int idx = tid; idx < spb * T; idx += blockDim.x) {
         const int sl = idx / T;
         const int t = idx - sl * T;
@@ -157,7 +168,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
         int cnt = 0;
         for (int t = 0; t < T; ++t) {
             acc += smooth_cost(c, s);
-            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y);
+            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y, n_cand);
             if (t + 1 < T) {  // the last draw cannot reach the risk cost
                 const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
                 const float4 w = disturbance<kNoise>(c, r);
@@ -185,6 +196,8 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
         ranks[(size_t)k * M + m] = rank;
         if (rank < c.n_tail) tail_idx[(size_t)k * c.n_tail + rank] = m;
     }
+    if (work && (tid & 63) == 0)
+        atomicAdd(&work[(item * 16 + (tid >> 6)) & (kWorkSlots - 1)], (unsigned long long)n_cand);
 }
 
 // Block-wide reductions over 256 threads (4 waves), fixed order.
