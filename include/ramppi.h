@@ -140,8 +140,12 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
  *   step_idx  call counter; it is the fourth Philox counter word, so the same
  *             (seed, step_idx, x0, V) reproduces the same result bit for bit.
  *   u0_host   NULL, or host memory for 2 floats: the first command of V+
- *             before any shift.  When set, the call waits for the step.
- * Enqueues three kernels on `stream` and returns. */
+ *             before any shift.  When set, the call returns as soon as the
+ *             update kernel has stored the command into mapped host memory
+ *             (it polls a completion word, so the kernel may still be
+ *             finishing its other writes; later work on `stream` is ordered
+ *             after it as usual).
+ * Enqueues two kernels on `stream`. */
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
 

@@ -81,7 +81,7 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, tab, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work;
+    size_t obs, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work;
     // gradient buffers (MPPI_F_GRAD)
     size_t ranks, tail_idx, act_list, n_act, J, states, rows, rpart, gcounter;
     int R, stride, n_lane_blocks;
@@ -93,7 +93,6 @@ Layout layout(const mppi_params* p) {
     Layout l;
     size_t o = 0;
     l.obs = o;     o += align_up(16 * (size_t)(p->n_obs > 0 ? p->n_obs : 1));
-    l.tab = o;     o += align_up(16 * (size_t)(p->n_obs > 0 ? (p->n_obs + 7) / 8 * 8 : 8));
     l.u = o;       o += align_up(8 * (size_t)p->K * p->T);
     l.S = o;       o += align_up(4 * (size_t)p->K);
     l.cvar = o;    o += align_up(4 * (size_t)p->K);
@@ -222,8 +221,9 @@ struct mppi_handle {
     Layout l;
     int n_tail, n_warm, device;
     char* ws;
-    float* u0_pinned;      // mapped, coherent pinned host memory (2 floats)
+    float* u0_pinned;      // mapped, coherent pinned host memory: 2 floats + completion word
     float* u0_pinned_dev;  // its device address
+    uint32_t u0_seq;       // last completion value requested
     bool timing;
     std::vector<hipEvent_t> ev;  // 3 per timed step: start, after rollout, end
     int n_timed;
@@ -234,7 +234,6 @@ namespace {
 ramppi::StepBuffers step_buffers(const mppi_handle* h, float* V_dev) {
     ramppi::StepBuffers bufs;
     bufs.obs = reinterpret_cast<const float4*>(h->ws + h->l.obs);
-    bufs.tab = reinterpret_cast<float4*>(h->ws + h->l.tab);
     bufs.V = V_dev;
     bufs.Vout = V_dev;
     bufs.u = reinterpret_cast<float2*>(h->ws + h->l.u);
@@ -363,8 +362,10 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     h->ws = static_cast<char*>(workspace_dev);
     h->timing = false;
     h->n_timed = 0;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->u0_pinned), 2 * sizeof(float),
+    h->u0_seq = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->u0_pinned), 4 * sizeof(float),
                                  hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) std::memset(h->u0_pinned, 0, 4 * sizeof(float));
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "hipHostMalloc");
@@ -423,6 +424,10 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
 
     ramppi::StepBuffers bufs = step_buffers(h, V_dev);
     bufs.u0_host = u0_host ? h->u0_pinned_dev : nullptr;
+    if (u0_host) {
+        h->u0_seq = h->u0_seq + 1 ? h->u0_seq + 1 : 1;  // never 0
+        c.u0_seq = h->u0_seq;
+    }
 
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_end = nullptr;
     if (h->timing && h->n_timed < kMaxTimedSteps) {
@@ -440,9 +445,23 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         h->n_timed++;
     }
     if (u0_host) {
-        // the update kernel stored the command into the mapped pinned buffer
-        e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "first-command readback");
+        // the update kernel stores the command and then the completion word
+        // into the mapped pinned buffer: poll the word (asking the stream now
+        // and then, so that a failed step still returns) rather than waiting
+        // for the whole stream
+        const uint32_t* word = reinterpret_cast<const uint32_t*>(h->u0_pinned + 2);
+        for (uint64_t spin = 1;; ++spin) {
+            if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == h->u0_seq) break;
+            if ((spin & 1023) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q == hipSuccess) {  // the step is complete, so is its word
+                    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == h->u0_seq) break;
+                    return fail(MPPI_EDEVICE, "the step completed without its first command");
+                }
+                if (q != hipErrorNotReady) return hip_fail(q, "first-command readback");
+            }
+            __builtin_ia32_pause();
+        }
         u0_host[0] = h->u0_pinned[0];
         u0_host[1] = h->u0_pinned[1];
     }
@@ -865,7 +884,6 @@ mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* cons
         fill_static(&c.c, p[i], g, n_tail, n_warm);
         char* base = b->ws + bl.ctl_base[i];
         c.obs = reinterpret_cast<const float4*>(base + l.obs);
-        c.tab = reinterpret_cast<float4*>(base + l.tab);
         c.V = V_dev[i];
         c.u = reinterpret_cast<float2*>(base + l.u);
         c.S = reinterpret_cast<float*>(base + l.S);

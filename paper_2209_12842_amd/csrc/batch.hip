@@ -1,9 +1,8 @@
 // Batched serving: one step of many independent controllers (uneven K, T, M
 // and obstacle counts) in three launches that a HIP graph can hold:
-//   k_batch_prep     one workgroup per controller: reads the controller's
-//                    measured state and call index from mapped host memory,
-//                    completes its per-step constants and writes its
-//                    obstacle table in the frame of its start position;
+//   k_batch_prep     one thread per controller: reads the controller's
+//                    measured state and call index from mapped host memory
+//                    and completes its per-step constants;
 //   k_batch_rollout  persistent: a fixed grid of workgroups takes
 //                    (controller, workgroup) items from a queue (an atomic
 //                    counter over an item list ordered by the host, by
@@ -34,20 +33,10 @@ __device__ __forceinline__ void set_dynamic(StepConst& c, const BatchCtl& b, con
     c.step_idx = in.step_idx;
 }
 
-__global__ void __launch_bounds__(256) k_batch_prep(BatchCtl* __restrict__ ctls,
-                                                    const BatchInput* __restrict__ inputs) {
-    __shared__ float f[2];
-    BatchCtl& b = ctls[blockIdx.x];
-    if (threadIdx.x == 0) {
-        const BatchInput in = inputs[blockIdx.x];
-        set_dynamic(b.c, b, in);
-        f[0] = in.x0[0];
-        f[1] = in.x0[1];
-    }
-    __syncthreads();
-    const int n_obs = b.c.n_obs;
-    const int n_pad = (n_obs + 7) & ~7;
-    for (int i = threadIdx.x; i < n_pad; i += blockDim.x) b.tab[i] = obstacle_entry(b.obs, n_obs, i, f[0], f[1]);
+__global__ void __launch_bounds__(64) k_batch_prep(BatchCtl* __restrict__ ctls, const BatchInput* __restrict__ inputs,
+                                                   int n_ctl) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < n_ctl) set_dynamic(ctls[i].c, ctls[i], inputs[i]);
 }
 
 __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restrict__ ctls,
@@ -65,13 +54,12 @@ __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restric
         const BatchCtl& b = ctls[__builtin_amdgcn_readfirstlane(cw.x)];
         const int w = __builtin_amdgcn_readfirstlane(cw.y);
         const StepConst c = b.c;
-        const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
         if (c.noise_kind == 1)
-            rollout_body<1>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
+            rollout_body<1>(c, b.obs, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
         else if (c.noise_kind == 2)
-            rollout_body<2>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
+            rollout_body<2>(c, b.obs, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
         else
-            rollout_body<0>(c, tab, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
+            rollout_body<0>(c, b.obs, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
         __syncthreads();  // LDS is reused by the next item
     }
     if (threadIdx.x == 0) {
@@ -96,7 +84,7 @@ __global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict
 }
 
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
-    hipLaunchKernelGGL(k_batch_prep, dim3(L.n_ctl), dim3(256), 0, stream, L.ctls, L.inputs);
+    hipLaunchKernelGGL(k_batch_prep, dim3((L.n_ctl + 63) / 64), dim3(64), 0, stream, L.ctls, L.inputs, L.n_ctl);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
     hipLaunchKernelGGL(k_batch_rollout, dim3(L.grid_rollout), dim3(256), L.lds_rollout, stream, L.ctls, L.items,
                        L.n_items, L.queue, L.work);

@@ -101,6 +101,8 @@ struct StepConst {
     uint32_t key0, key1, step_idx, flags;
     int32_t use_bdry, use_term, use_ctrl, scale_risk, debug;
     int32_t grad;        // record tail ranks for the gradient of the free energy
+    uint32_t u0_seq;     // nonzero: after the first command, store this value to
+                         // the word after it in mapped host memory (the host waits on it)
 };
 
 struct State {
@@ -160,19 +162,9 @@ __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s)
     return q;
 }
 
-// Eight obstacle-table entries, read together (scalar loads of 128 bytes).
-struct __attribute__((aligned(128))) ObstacleOct {
-    float4 o[8];
-};
-
-// Obstacle table entry i, in the frame of the start position (cx, cy relative
-// to x0): (-2 cx, -2 cy, r^2 - cx^2 - cy^2, q) with
-// q = (1 + 2^-16) r^2 + 2^-15 (cx^2 + cy^2), the squared reach of the
-// broad-phase test below.  Padding entries are (0, 0, -inf, -inf).
-//
-// Exact test (Eq. 22): the point p is inside disc i iff
-// |p|^2 + tab.x px + tab.y py < tab.z, evaluated as two FMAs on
-// rho = |p|^2 and one compare.
+// Obstacle test (Eq. 22) on the table of a step (obstacle_entry): the point
+// p is inside disc i iff |p|^2 + tab.x px + tab.y py < tab.z, evaluated as
+// two FMAs on rho = |p|^2 and one compare.
 
 // Wave-wide minimum and maximum of a float over all 64 lanes (every lane
 // active), on order-preserving integer keys: the key of x flips the magnitude

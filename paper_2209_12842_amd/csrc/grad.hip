@@ -127,7 +127,6 @@ __global__ void __launch_bounds__(256) k_grad_reduce(int T, int G3, GradArgs a) 
         acc = wave_sum(acc);
         if (lane == 0) a.rpart[(size_t)b * 2 * T + q] = acc;
     }
-    __threadfence();
     __syncthreads();
     if (tid == 0) {
         const unsigned done = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -139,7 +138,15 @@ __global__ void __launch_bounds__(256) k_grad_reduce(int T, int G3, GradArgs a) 
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
     for (int q = tid; q < 2 * T; q += 256) {
         float acc = 0.0f;
-        for (int bb = 0; bb < G3; ++bb) acc += a.rpart[(size_t)bb * 2 * T + q];
+        int bb = 0;
+        for (; bb + 16 <= G3; bb += 16) {  // 16 loads in flight, then the sums in order
+            float pv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) pv[i] = a.rpart[(size_t)(bb + i) * 2 * T + q];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc += pv[i];
+        }
+        for (; bb < G3; ++bb) acc += a.rpart[(size_t)bb * 2 * T + q];
         a.grad_out[q] = acc;
     }
 }
@@ -158,7 +165,6 @@ __global__ void __launch_bounds__(256) k_update_grad(StepConst c, int G, int par
 hipError_t launch_grad(const StepConst& c, const StepBuffers& b, const GradArgs& a, const GradOut& go, int block,
                        size_t lds_rollout, int G, size_t lds_update, int n_lane_blocks, hipStream_t stream) {
     const int n_dist_wg = (c.K + c.spb - 1) / c.spb;
-    launch_obstacle_frame(c, b, stream);
     (void)launch_rollout(c, b, block, lds_rollout, n_dist_wg, stream, a.ranks_w, a.tail_w);
     hipLaunchKernelGGL(k_update_grad, dim3(G), dim3(256), lds_update, stream, c, G, update_parts(c.T), b.S, b.cvar,
                        b.u, b.S_tilde, b.part, b.counter, b.w_hat, go);

@@ -1,13 +1,13 @@
 // Kernels of the RA-MPPI control step for gfx950.
 //
-// One step is three launches on the caller's stream:
-//   k_obstacle_frame  the obstacle table in the frame of the start position;
+// One step is two launches on the caller's stream:
 //   k_rollout   nominal workgroups (one lane per sample k: sampled controls,
 //               nominal rollout, cost S; Eq. 1-3) and disturbed workgroups
 //               (one lane per pair (k, m): disturbed rollout and risk cost L,
 //               Eq. 6, 9; then scaling and the CVaR tail mean per sample,
-//               Eq. 10-13, 18-19), with the sample's controls staged in LDS
-//               and the obstacle table read through scalar loads;
+//               Eq. 10-13, 18-19); every workgroup stages the obstacle table
+//               in the frame of the start position into LDS, and the
+//               disturbed ones also their samples' controls;
 //   k_update    per 256-sample chunk: S~ = S + J_C (Eq. 14-16), the chunk's
 //               minimum, weight sum and weighted control sums (Eq. 17); the
 //               last workgroup merges the chunks (log-sum-exp), forms V+
@@ -19,23 +19,14 @@
 
 namespace ramppi {
 
-// Obstacle table of one step in the local frame centred on the start
-// position (see obstacle_entry), padded to a multiple of 8 entries.
-__global__ void __launch_bounds__(256) k_obstacle_frame(const float4* __restrict__ obs, int n_obs, float fx,
-                                                        float fy, float4* __restrict__ tab) {
-    const int n_pad = (n_obs + 7) & ~7;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += gridDim.x * blockDim.x)
-        tab[i] = obstacle_entry(obs, n_obs, i, fx, fy);
-}
-
 template <int kNoise>
-__global__ void __launch_bounds__(1024) k_rollout(StepConst c, const ObstacleOct* __restrict__ tab,
+__global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __restrict__ obs,
                                                   const float* __restrict__ V, float2* __restrict__ u_out,
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
                                                   float* __restrict__ L_out, int* __restrict__ ranks,
                                                   int* __restrict__ tail_idx, unsigned long long* __restrict__ work) {
     extern __shared__ float2 smem[];
-    rollout_body<kNoise>(c, tab, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx, work);
+    rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx, work);
 }
 
 __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
@@ -89,24 +80,17 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
 
 // ---- launchers ----
 
-void launch_obstacle_frame(const StepConst& c, const StepBuffers& b, hipStream_t stream) {
-    if (c.n_obs > 0)
-        hipLaunchKernelGGL(k_obstacle_frame, dim3((c.n_obs + 255) / 256), dim3(256), 0, stream, b.obs, c.n_obs,
-                           c.fx, c.fy, b.tab);
-}
-
 hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
                           hipStream_t stream, int* ranks, int* tail_idx) {
-    const ObstacleOct* tab = reinterpret_cast<const ObstacleOct*>(b.tab);
     const dim3 grid(c.n_nom_wg + n_dist_wg);
     if (c.noise_kind == 1)
-        hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
+        hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
                            ranks, tail_idx, b.work);
     else if (c.noise_kind == 2)
-        hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
+        hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
                            ranks, tail_idx, b.work);
     else
-        hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, tab, b.V, b.u, b.S, b.cvar, b.L,
+        hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
                            ranks, tail_idx, b.work);
     return hipGetLastError();
 }
@@ -122,7 +106,6 @@ size_t update_lds_bytes(int T, int G) {
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
                        size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
     const int n_dist_wg = (c.K + c.spb - 1) / c.spb;
-    launch_obstacle_frame(c, b, stream);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
     (void)launch_rollout(c, b, block, lds_rollout, n_dist_wg, stream, nullptr, nullptr);
     if (ev_mid) (void)hipEventRecord(ev_mid, stream);

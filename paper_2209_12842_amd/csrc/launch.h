@@ -13,7 +13,6 @@ namespace ramppi {
 // Device buffers of one step (all inside the caller's workspace except V).
 struct StepBuffers {
     const float4* obs;  // n_obs x (cx, cy, r, 0)
-    float4* tab;        // n_obs obstacle table in the local frame
     const float* V;     // T x 2, the mean sequence (read by k_rollout)
     float* Vout;        // T x 2, V+ (written by k_merge; the same memory as V)
     float2* u;          // T x K sampled controls, time-major
@@ -34,7 +33,6 @@ struct StepBuffers {
 struct BatchCtl {
     StepConst c;
     const float4* obs;
-    float4* tab;
     float* V;
     float2* u;
     float* S;
@@ -97,7 +95,6 @@ int update_parts(int T);
 size_t update_lds_bytes(int T, int G);
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
                        size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid);
-void launch_obstacle_frame(const StepConst& c, const StepBuffers& b, hipStream_t stream);
 hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
                           hipStream_t stream, int* ranks, int* tail_idx);
 hipError_t launch_grad(const StepConst& c, const StepBuffers& b, const GradArgs& a, const GradOut& go, int block,

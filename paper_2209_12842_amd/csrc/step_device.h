@@ -14,9 +14,11 @@ struct GradOut {
     int* n_act;
 };
 
-// One entry of the obstacle table of a step, in the local frame centred on
-// the start position (fx, fy): (-2 cx, -2 cy, r^2 - cx^2 - cy^2, 0) for
-// i < n_obs; entries up to the next multiple of 8 can never be hit (-inf).
+// Entry i of the obstacle table of a step, in the local frame centred on the
+// start position (fx, fy), with cx, cy relative to it:
+// (-2 cx, -2 cy, r^2 - cx^2 - cy^2, q), q = (1 + 2^-16) r^2 + 2^-15 (cx^2 + cy^2)
+// the squared reach of the broad-phase test (obstacle_hits_culled); entries
+// i >= n_obs are padding that no point can hit, (0, 0, -inf, -inf).
 __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs, int n_obs, int i, float fx,
                                                  float fy) {
     if (i < n_obs) {
@@ -37,7 +39,8 @@ __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs,
 //   float  means[spb]     mean risk cost per sample (risk scaling)
 //   float4 otab[64 n_grp] the obstacle table, padded to groups of 64 entries
 //                         (16-byte aligned; n_grp = ceil(n_obs / 64))
-// rollout_lds_floats gives the offset of otab and the total, in floats.
+// rollout_otab_offset gives the offset of otab in floats.  Every workgroup
+// writes otab from the raw obstacles before its rollouts.
 __host__ __device__ __forceinline__ int rollout_otab_offset(int spb, int T, int M) {
     return (2 * spb * T + 2 * spb * M + spb + 3) & ~3;
 }
@@ -85,7 +88,7 @@ __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* 
 // (spb samples of M lanes).  Ends with every lane past its last LDS access
 // (the caller may reuse the LDS after a barrier).
 template <int kNoise>
-__device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleOct* __restrict__ tab,
+__device__ __forceinline__ void rollout_body(const StepConst& c, const float4* __restrict__ obs,
                                              const float* __restrict__ V, float2* __restrict__ u_out,
                                              float* __restrict__ S_out, float* __restrict__ cvar_out,
                                              float* __restrict__ L_out, int item, float2* smem,
@@ -99,12 +102,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const ObstacleO
     const int spb = c.spb, M = c.M, T = c.T;
     const int n_grp = rollout_n_grp(c.n_obs);
     float4* otab = reinterpret_cast<float4*>(reinterpret_cast<float*>(smem) + rollout_otab_offset(spb, T, M));
-    {
-        const float4* tab4 = reinterpret_cast<const float4*>(tab);
-        const int n_pad = ((c.n_obs + 7) >> 3) * 8;
-        for (int i = tid; i < n_grp * 64; i += blockDim.x)
-            otab[i] = (i < n_pad) ? tab4[i] : make_float4(0.0f, 0.0f, -__builtin_inff(), -__builtin_inff());
-    }
+    for (int i = tid; i < n_grp * 64; i += blockDim.x) otab[i] = obstacle_entry(obs, c.n_obs, i, c.fx, c.fy);
     int n_cand = 0;  // broad-phase candidates of this wave (wave-uniform)
 
     if (item < c.n_nom_wg) {
@@ -269,7 +267,18 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         const int ka = pr * slice, kb = min(n, ka + slice);
         const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
-        for (int k = ka; k < kb; ++k) {
+        int k = ka;
+        for (; k + 16 <= kb; k += 16) {  // 16 loads in flight, then the sums in order
+            float2 uu[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) uu[i] = ut[k + i];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                ax = __fmaf_rn(wsh[k + i], uu[i].x, ax);
+                ay = __fmaf_rn(wsh[k + i], uu[i].y, ay);
+            }
+        }
+        for (; k < kb; ++k) {
             const float2 uu = ut[k];
             ax = __fmaf_rn(wsh[k], uu.x, ax);
             ay = __fmaf_rn(wsh[k], uu.y, ay);
@@ -289,9 +298,10 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         pb[1] = Z_b;
     }
 
-    // 3. the last workgroup to finish merges every chunk; every thread makes
-    // its own stores visible at device scope before thread 0 signals
-    __threadfence();
+    // 3. the last workgroup to finish merges every chunk.  Thread 0's
+    // device-scope release (after the barrier that orders the other threads'
+    // stores before it) publishes the chunk's partials; the last workgroup's
+    // acquire makes them visible to all its threads.
     __syncthreads();
     if (tid == 0) {
         const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -317,7 +327,15 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
     const float invZ = 1.0f / Z;
     for (int j = tid; j < 2 * T; j += 256) {
         float acc = 0.0f;
-        for (int bb = 0; bb < G; ++bb) acc = __fmaf_rn(part[(size_t)bb * stride + 2 + j], scale[bb], acc);
+        int bb = 0;
+        for (; bb + 16 <= G; bb += 16) {  // 16 loads in flight, then the sums in order
+            float pv[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) pv[i] = part[(size_t)(bb + i) * stride + 2 + j];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc = __fmaf_rn(pv[i], scale[bb + i], acc);
+        }
+        for (; bb < G; ++bb) acc = __fmaf_rn(part[(size_t)bb * stride + 2 + j], scale[bb], acc);
         vp[j] = acc * invZ;
     }
     __syncthreads();
@@ -357,9 +375,13 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         if (shift) src = min(j + 2, 2 * T - 2 + (j & 1));
         V[j] = vp[src];
     }
-    if (tid < 2) {
-        u0[tid] = vp[tid];
-        if (u0_host) u0_host[tid] = vp[tid];  // mapped pinned host memory
+    if (tid < 2) u0[tid] = vp[tid];
+    if (tid == 0 && u0_host) {  // mapped pinned host memory
+        u0_host[0] = vp[0];
+        u0_host[1] = vp[1];
+        if (c.u0_seq)  // completion word, ordered after the command at system scope
+            __hip_atomic_store(reinterpret_cast<unsigned*>(u0_host + 2), c.u0_seq, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (c.debug) {
         for (int k = tid; k < K; k += 256) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
