@@ -58,7 +58,8 @@ enum {
     MPPI_F_DEBUG = 1u,            /* also write L (K x M) and normalised weights */
     MPPI_F_SHIFT = 2u,            /* V <- V+ shifted left by one step, last repeated */
     MPPI_F_ALLOW_ZERO_NOISE = 4u, /* accept zero variances (then gamma must be 0) */
-    MPPI_F_GRAD = 8u              /* workspace also holds the buffers of mppi_grad */
+    MPPI_F_GRAD = 8u,             /* workspace also holds the buffers of mppi_grad */
+    MPPI_F_SPLIT_UPDATE = 16u     /* always run the update as a launch of its own (see mppi_step) */
 };
 
 /* Library limits (MPPI_EUNSUPPORTED beyond them). */
@@ -145,7 +146,11 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
  *             (it polls a completion word, so the kernel may still be
  *             finishing its other writes; later work on `stream` is ordered
  *             after it as usual).
- * Enqueues two kernels on `stream`. */
+ * Enqueues one kernel on `stream` when every workgroup of the step can be
+ * resident on the device at once (the workgroups that finish a chunk of
+ * samples then also run its update, and the last one the merge), else two
+ * (rollouts, then the update); MPPI_F_SPLIT_UPDATE forces two.  Both give
+ * the same bits. */
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libramppi.so")
 HEADER = os.path.join(os.path.dirname(_PKG), "include", "ramppi.h")
 
 MPPI_OK, MPPI_EINVAL, MPPI_ENOMEM, MPPI_EDEVICE, MPPI_EUNSUPPORTED = 0, -1, -2, -3, -4
-MPPI_F_DEBUG, MPPI_F_SHIFT, MPPI_F_ALLOW_ZERO_NOISE, MPPI_F_GRAD = 1, 2, 4, 8
+MPPI_F_DEBUG, MPPI_F_SHIFT, MPPI_F_ALLOW_ZERO_NOISE, MPPI_F_GRAD, MPPI_F_SPLIT_UPDATE = 1, 2, 4, 8, 16
 STATUS_NAMES = {0: "MPPI_OK", -1: "MPPI_EINVAL", -2: "MPPI_ENOMEM", -3: "MPPI_EDEVICE", -4: "MPPI_EUNSUPPORTED"}
 
 
@@ -172,12 +172,12 @@ class Controller:
     torch stream of that device."""
 
     def __init__(self, params: dict, obstacles, device="cuda", debug: bool = False,
-                 allow_zero_noise: bool = False, grad: bool = False):
+                 allow_zero_noise: bool = False, grad: bool = False, split_update: bool = False):
         torch = _torch()
         L = lib()
         obs = np.ascontiguousarray(np.asarray(obstacles, dtype=np.float32).reshape(-1, 3))
         flags = ((MPPI_F_DEBUG if debug else 0) | (MPPI_F_ALLOW_ZERO_NOISE if allow_zero_noise else 0)
-                 | (MPPI_F_GRAD if grad else 0))
+                 | (MPPI_F_GRAD if grad else 0) | (MPPI_F_SPLIT_UPDATE if split_update else 0))
         self.params = dict(params)
         self.p = make_params(params, obs.shape[0], flags)
         nbytes = L.mppi_workspace_bytes(ctypes.byref(self.p))

@@ -81,7 +81,7 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work;
+    size_t obs, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work, chunk, fuse;
     // gradient buffers (MPPI_F_GRAD)
     size_t ranks, tail_idx, act_list, n_act, J, states, rows, rpart, gcounter;
     int R, stride, n_lane_blocks;
@@ -103,6 +103,8 @@ Layout layout(const mppi_params* p) {
     l.u0 = o;      o += align_up(8);
     l.counter = o; o += align_up(4);
     l.work = o;    o += align_up(8 * (size_t)ramppi::kWorkSlots);
+    l.chunk = o;   o += align_up(4 * (size_t)g.G);
+    l.fuse = o;    o += align_up(sizeof(ramppi::FuseArgs));
     l.ranks = l.tail_idx = l.act_list = l.n_act = l.J = l.states = l.rows = l.rpart = l.gcounter = 0;
     l.R = l.stride = l.n_lane_blocks = 0;
     if (p->flags & MPPI_F_GRAD) {
@@ -224,6 +226,7 @@ struct mppi_handle {
     float* u0_pinned;      // mapped, coherent pinned host memory: 2 floats + completion word
     float* u0_pinned_dev;  // its device address
     uint32_t u0_seq;       // last completion value requested
+    bool fuse;             // one launch per step (the whole grid is resident at once)
     bool timing;
     std::vector<hipEvent_t> ev;  // 3 per timed step: start, after rollout, end
     int n_timed;
@@ -247,6 +250,7 @@ ramppi::StepBuffers step_buffers(const mppi_handle* h, float* V_dev) {
     bufs.counter = reinterpret_cast<unsigned*>(h->ws + h->l.counter);
     bufs.u0_host = nullptr;
     bufs.work = nullptr;
+    bufs.chunk_ctr = reinterpret_cast<unsigned*>(h->ws + h->l.chunk);
     return bufs;
 }
 
@@ -272,7 +276,8 @@ mppi_status mppi_validate(const mppi_params* p) {
     if (p->K < 1 || p->T < 1 || p->M < 1 || p->n_obs < 0)
         return fail(MPPI_EINVAL, "sizes must satisfy K, T, M >= 1 and n_obs >= 0 (got K=%d T=%d M=%d n_obs=%d)",
                     p->K, p->T, p->M, p->n_obs);
-    if (p->flags & ~(uint32_t)(MPPI_F_DEBUG | MPPI_F_SHIFT | MPPI_F_ALLOW_ZERO_NOISE | MPPI_F_GRAD))
+    if (p->flags &
+        ~(uint32_t)(MPPI_F_DEBUG | MPPI_F_SHIFT | MPPI_F_ALLOW_ZERO_NOISE | MPPI_F_GRAD | MPPI_F_SPLIT_UPDATE))
         return fail(MPPI_EINVAL, "unknown flag bits 0x%x", p->flags);
     if (!(finite(p->dt) && p->dt > 0)) return fail(MPPI_EINVAL, "dt must be finite and > 0");
     if (!(finite(p->wheelbase) && p->wheelbase > 0)) return fail(MPPI_EINVAL, "wheelbase must be finite and > 0");
@@ -386,7 +391,31 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     e = hipMemcpyAsync(h->ws + l.obs, staged.data(), 16 * (size_t)p->n_obs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.counter, 0, 4, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.work, 0, 8 * (size_t)ramppi::kWorkSlots, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.chunk, 0, 4 * (size_t)h->g.G, s);
     if (e == hipSuccess && (p->flags & MPPI_F_GRAD)) e = hipMemsetAsync(h->ws + l.gcounter, 0, 4, s);
+    // one launch per step when every workgroup of the step can be resident at
+    // once (the update then runs in the workgroups that finish each chunk)
+    h->fuse = false;
+    ramppi::FuseArgs fa;
+    std::memset(&fa, 0, sizeof fa);
+    if (e == hipSuccess && !(p->flags & MPPI_F_SPLIT_UPDATE)) {
+        int per_cu = 0, n_cu = 0;
+        e = ramppi::fused_rollout_capacity((int)p->noise_kind, h->g.block,
+                                           std::max(h->g.lds_rollout, h->g.lds_update), &per_cu);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        const int64_t grid = h->g.n_nom_wg + ((int64_t)p->K + h->g.spb - 1) / h->g.spb;
+        h->fuse = e == hipSuccess && (int64_t)per_cu * n_cu >= grid;
+        fa.chunk_ctr = reinterpret_cast<unsigned*>(h->ws + l.chunk);
+        fa.counter = reinterpret_cast<unsigned*>(h->ws + l.counter);
+        fa.S_tilde = reinterpret_cast<float*>(h->ws + l.S_tilde);
+        fa.part = reinterpret_cast<float*>(h->ws + l.part);
+        fa.u0 = reinterpret_cast<float*>(h->ws + l.u0);
+        fa.u0_host = h->u0_pinned_dev;
+        fa.w_hat = reinterpret_cast<float*>(h->ws + l.w_hat);
+        fa.G = h->g.G;
+        fa.parts = ramppi::update_parts(p->T);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->ws + l.fuse, &fa, sizeof fa, hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipHostFree(h->u0_pinned);
@@ -437,7 +466,9 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         ev_end = e3[2];
     }
     if (h->timing) bufs.work = reinterpret_cast<unsigned long long*>(h->ws + h->l.work);
-    hipError_t e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_update, s, ev_start, ev_mid);
+    const ramppi::FuseArgs* fa = h->fuse ? reinterpret_cast<const ramppi::FuseArgs*>(h->ws + h->l.fuse) : nullptr;
+    hipError_t e =
+        ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_update, s, ev_start, ev_mid, fa);
     if (e != hipSuccess) return hip_fail(e, "step launch");
     if (ev_end) {
         e = hipEventRecord(ev_end, s);

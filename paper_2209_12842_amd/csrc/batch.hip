@@ -74,7 +74,7 @@ __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restric
 __global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict__ ctls,
                                                       const int2* __restrict__ uitems) {
     extern __shared__ float bush[];
-    __shared__ float red[4];
+    __shared__ float red[16];
     __shared__ int is_last;
     const int2 cb = uitems[blockIdx.x];
     const BatchCtl& b = ctls[cb.x];

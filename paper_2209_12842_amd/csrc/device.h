@@ -166,39 +166,27 @@ __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s)
 // p is inside disc i iff |p|^2 + tab.x px + tab.y py < tab.z, evaluated as
 // two FMAs on rho = |p|^2 and one compare.
 
-// Wave-wide minimum and maximum of a float over all 64 lanes (every lane
-// active), on order-preserving integer keys: the key of x flips the magnitude
-// bits of negative values, so signed-integer order equals float order (NaN
-// excepted).  Rows of 16 lanes reduce with DPP lane permutations, the four
-// row results are read into SGPRs and combined on the scalar unit.
-__device__ __forceinline__ int f32_key(float x) {
-    const int i = __float_as_int(x);
-    return i ^ (int)((uint32_t)(i >> 31) >> 1);
-}
-
-__device__ __forceinline__ float key_f32(int k) { return __int_as_float(k ^ (int)((uint32_t)(k >> 31) >> 1)); }
-
+// Wave-wide maximum of a 32-bit unsigned value over all 64 lanes (every lane
+// active): rows of 16 lanes reduce with DPP lane permutations, the four row
+// results are read into SGPRs and combined on the scalar unit.  The result
+// is wave-uniform.  Non-negative floats order like their bit patterns, so it
+// also serves for the maximum of |x|.
 template <int kCtrl>
-__device__ __forceinline__ int dpp_i32(int v, int old) {
-    return __builtin_amdgcn_update_dpp(old, v, kCtrl, 0xF, 0xF, false);
+__device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v) {
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xF, 0xF, false);
+    return v > o ? v : o;
 }
 
-__device__ __forceinline__ int wave_min_key(int v) {
-    v = min(v, dpp_i32<0xB1>(v, INT_MAX));   // quad_perm [1,0,3,2]
-    v = min(v, dpp_i32<0x4E>(v, INT_MAX));   // quad_perm [2,3,0,1]
-    v = min(v, dpp_i32<0x141>(v, INT_MAX));  // row_half_mirror
-    v = min(v, dpp_i32<0x140>(v, INT_MAX));  // row_mirror
-    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
-
-__device__ __forceinline__ int wave_max_key(int v) {
-    v = max(v, dpp_i32<0xB1>(v, INT_MIN));
-    v = max(v, dpp_i32<0x4E>(v, INT_MIN));
-    v = max(v, dpp_i32<0x141>(v, INT_MIN));
-    v = max(v, dpp_i32<0x140>(v, INT_MIN));
-    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+    v = dpp_max_u32<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = dpp_max_u32<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = dpp_max_u32<0x141>(v);  // row_half_mirror
+    v = dpp_max_u32<0x140>(v);  // row_mirror
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
 }
 
 __device__ __forceinline__ float lane_f32(float v, int lane) {
@@ -206,23 +194,28 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
 }
 
 // Number of obstacle discs strictly containing the point, for a wave whose
-// points lie close together (the M draws of one sample).  Broad phase: the
-// wave's bounding box [x0, x1] x [y0, y1] against every disc, lane j testing
+// points lie close together (the M draws of one sample).  Broad phase: a box
+// around the wave's points, [xc - Rx, xc + Rx] x [yc - Ry, yc + Ry] with
+// (xc, yc) the first lane's point and Rx, Ry the largest distances of the
+// lanes' points from it along x and y, against every disc, lane j testing
 // entry 64 g + j of the table staged in LDS (otab, n_grp groups of 64):
 // d2 = squared distance from the disc centre to the box, candidate iff
-// d2 < q + 2^-15 P^2, where P^2 = max(|x0|, |x1|)^2 + max(|y0|, |y1|)^2 bounds
-// |p|^2 over the box.  The margin exceeds the rounding error of both this
-// test and the exact test by more than twenty times (each is a few units in
-// the last place of r^2 + |c|^2 + |p|^2), so a disc that is not a candidate
-// fails the exact test in every lane.  Narrow phase: the exact test of the
-// candidates, their entries broadcast from lane j.  Every lane of the wave
-// must be active.  n_cand counts the candidates (wave-uniform).
+// d2 < q + 2^-15 P^2, where P^2 = (|xc| + Rx)^2 + (|yc| + Ry)^2 bounds |p|^2
+// over the box.  The margin exceeds the rounding error of both this test and
+// the exact test (each a few units in the last place of r^2 + |c|^2 + |p|^2,
+// the box edges a few units in the last place of P) by more than twenty
+// times, so a disc that is not a candidate fails the exact test in every
+// lane.  Narrow phase: the exact test of the candidates, their entries
+// broadcast from lane j.  Every lane of the wave must be active.  n_cand
+// counts the candidates (wave-uniform).
 __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float px, float py,
                                                     int& n_cand) {
-    const int kx = f32_key(px), ky = f32_key(py);
-    const float x0 = key_f32(wave_min_key(kx)), x1 = key_f32(wave_max_key(kx));
-    const float y0 = key_f32(wave_min_key(ky)), y1 = key_f32(wave_max_key(ky));
-    const float ax = fmaxf(fabsf(x0), fabsf(x1)), ay = fmaxf(fabsf(y0), fabsf(y1));
+    const float xc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px)));
+    const float yc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py)));
+    const float rx = __uint_as_float(wave_max_u32(__float_as_uint(fabsf(px - xc))));
+    const float ry = __uint_as_float(wave_max_u32(__float_as_uint(fabsf(py - yc))));
+    const float x0 = xc - rx, x1 = xc + rx, y0 = yc - ry, y1 = yc + ry;
+    const float ax = fabsf(xc) + rx, ay = fabsf(yc) + ry;
     const float p2 = 3.0517578125e-05f * __fmaf_rn(ax, ax, ay * ay);  // 2^-15 P^2
     const float rho = __fmaf_rn(px, px, py * py);
     const int lane = threadIdx.x & 63;

@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_update_grad(StepConst c, int G, int par
                                                      float* __restrict__ S_tilde, float* part, unsigned* counter,
                                                      float* __restrict__ w_hat, GradOut go) {
     extern __shared__ float ush[];
-    __shared__ float red[4];
+    __shared__ float red[16];
     __shared__ int is_last;
     update_body(c, blockIdx.x, G, parts, S, cvar, u, S_tilde, part, counter, nullptr, nullptr, nullptr, w_hat, ush,
                 red, &is_last, &go);

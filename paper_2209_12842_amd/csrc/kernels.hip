@@ -19,14 +19,25 @@
 
 namespace ramppi {
 
-template <int kNoise>
+template <int kNoise, bool kFuse>
 __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __restrict__ obs,
                                                   const float* __restrict__ V, float2* __restrict__ u_out,
                                                   float* __restrict__ S_out, float* __restrict__ cvar_out,
                                                   float* __restrict__ L_out, int* __restrict__ ranks,
-                                                  int* __restrict__ tail_idx, unsigned long long* __restrict__ work) {
+                                                  int* __restrict__ tail_idx, unsigned long long* __restrict__ work,
+                                                  const FuseArgs* __restrict__ fa) {
     extern __shared__ float2 smem[];
     rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx, work);
+    if constexpr (kFuse) {
+        __shared__ float red[16];
+        __shared__ int flag_sh;
+        __shared__ int fin_sh[8];
+        const FuseArgs f = *fa;
+        // V is read by the rollouts and rewritten by the merge, which runs
+        // only after every rollout of the step has finished
+        fused_update(c, f, blockIdx.x, S_out, cvar_out, u_out, const_cast<float*>(V),
+                     reinterpret_cast<float*>(smem), red, &flag_sh, fin_sh);
+    }
 }
 
 __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
@@ -35,7 +46,7 @@ __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, c
                                                 float* __restrict__ V, float* __restrict__ u0,
                                                 float* __restrict__ u0_host, float* __restrict__ w_hat) {
     extern __shared__ float ush[];
-    __shared__ float red[4];
+    __shared__ float red[16];
     __shared__ int is_last;
     update_body(c, blockIdx.x, G, parts, S, cvar, u, S_tilde, part, counter, V, u0, u0_host, w_hat, ush, red,
                 &is_last);
@@ -80,19 +91,33 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
 
 // ---- launchers ----
 
+template <bool kFuse>
+static void launch_rollout_t(const StepConst& c, const StepBuffers& b, dim3 grid, int block, size_t lds,
+                             hipStream_t stream, int* ranks, int* tail_idx, const FuseArgs* fa) {
+    if (c.noise_kind == 1)
+        hipLaunchKernelGGL((k_rollout<1, kFuse>), grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
+                           b.L, ranks, tail_idx, b.work, fa);
+    else if (c.noise_kind == 2)
+        hipLaunchKernelGGL((k_rollout<2, kFuse>), grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
+                           b.L, ranks, tail_idx, b.work, fa);
+    else
+        hipLaunchKernelGGL((k_rollout<0, kFuse>), grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
+                           b.L, ranks, tail_idx, b.work, fa);
+}
+
 hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
                           hipStream_t stream, int* ranks, int* tail_idx) {
-    const dim3 grid(c.n_nom_wg + n_dist_wg);
-    if (c.noise_kind == 1)
-        hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds_rollout, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
-                           ranks, tail_idx, b.work);
-    else if (c.noise_kind == 2)
-        hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds_rollout, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
-                           ranks, tail_idx, b.work);
-    else
-        hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds_rollout, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
-                           ranks, tail_idx, b.work);
+    launch_rollout_t<false>(c, b, dim3(c.n_nom_wg + n_dist_wg), block, lds_rollout, stream, ranks, tail_idx,
+                            nullptr);
     return hipGetLastError();
+}
+
+hipError_t fused_rollout_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu) {
+    if (noise_kind == 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<1, true>, block, lds);
+    if (noise_kind == 2)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<2, true>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<0, true>, block, lds);
 }
 
 int update_parts(int T) { return T >= 256 ? 1 : 256 / T; }
@@ -104,13 +129,20 @@ size_t update_lds_bytes(int T, int G) {
 }
 
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
-                       size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
-    const int n_dist_wg = (c.K + c.spb - 1) / c.spb;
+                       size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid,
+                       const FuseArgs* fa) {
+    const dim3 grid(c.n_nom_wg + (c.K + c.spb - 1) / c.spb);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
-    (void)launch_rollout(c, b, block, lds_rollout, n_dist_wg, stream, nullptr, nullptr);
-    if (ev_mid) (void)hipEventRecord(ev_mid, stream);
-    hipLaunchKernelGGL(k_update, dim3(G), dim3(256), lds_update, stream, c, G, update_parts(c.T), b.S, b.cvar, b.u,
-                       b.S_tilde, b.part, b.counter, b.Vout, b.u0, b.u0_host, b.w_hat);
+    if (fa) {  // one launch: the update runs in the workgroups that finish each chunk
+        launch_rollout_t<true>(c, b, grid, block, lds_rollout > lds_update ? lds_rollout : lds_update, stream,
+                               nullptr, nullptr, fa);
+        if (ev_mid) (void)hipEventRecord(ev_mid, stream);
+    } else {
+        launch_rollout_t<false>(c, b, grid, block, lds_rollout, stream, nullptr, nullptr, nullptr);
+        if (ev_mid) (void)hipEventRecord(ev_mid, stream);
+        hipLaunchKernelGGL(k_update, dim3(G), dim3(256), lds_update, stream, c, G, update_parts(c.T), b.S, b.cvar,
+                           b.u, b.S_tilde, b.part, b.counter, b.Vout, b.u0, b.u0_host, b.w_hat);
+    }
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ struct StepBuffers {
     float* u0;          // 2
     float* u0_host;     // 2 floats of mapped pinned host memory, or null
     unsigned long long* work;  // kWorkSlots broad-phase candidate counters, or null
+    unsigned* chunk_ctr;       // G per-chunk contributor counters (zero between launches)
 };
 
 // One controller of a batch, in device memory: its step constants (the static
@@ -93,10 +94,16 @@ struct GradArgs {
 
 int update_parts(int T);
 size_t update_lds_bytes(int T, int G);
+// One step on `stream`: with fa (the update's buffers in device memory) a
+// single launch whose workgroups also run the update, else the rollout launch
+// and then the update launch.
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
-                       size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid);
+                       size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid,
+                       const FuseArgs* fa);
 hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
                           hipStream_t stream, int* ranks, int* tail_idx);
+// Workgroups of the one-launch step (rollouts and update) resident per CU.
+hipError_t fused_rollout_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu);
 hipError_t launch_grad(const StepConst& c, const StepBuffers& b, const GradArgs& a, const GradOut& go, int block,
                        size_t lds_rollout, int G, size_t lds_update, int n_lane_blocks, hipStream_t stream);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t stream);

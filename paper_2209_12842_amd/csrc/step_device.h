@@ -198,82 +198,95 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         atomicAdd(&work[(item * 16 + (tid >> 6)) & (kWorkSlots - 1)], (unsigned long long)n_cand);
 }
 
-// Block-wide reductions over 256 threads (4 waves), fixed order.
-__device__ __forceinline__ float block_min_256(float v, float* red) {
-    v = wave_min(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// Sum and minimum of 256 values held in LDS (v[0..255]) in a fixed order that
+// does not depend on the workgroup size: wave-sized segments of 64 values are
+// reduced by the butterflies of wave_sum / wave_min, the four segment results
+// combined as (s0 + s1) + (s2 + s3).  Every thread of the workgroup (a
+// multiple of 64 threads) must call them; the result is returned to all.
+// red holds at least 16 floats of LDS.
+__device__ __forceinline__ float seg_sum_256(const float* v, float* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();  // v written
+    for (int sg = wv; sg < 4; sg += nw) {
+        const float x = wave_sum(v[64 * sg + lane]);
+        if (lane == 0) red[sg] = x;
+    }
     __syncthreads();
-    if (lane == 0) red[wv] = v;
-    __syncthreads();
-    return fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
+    const float r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();  // red and v free again
+    return r;
 }
 
-__device__ __forceinline__ float block_sum_256(float v, float* red) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+__device__ __forceinline__ float seg_min_256(const float* v, float* red) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
-    if (lane == 0) red[wv] = v;
+    for (int sg = wv; sg < 4; sg += nw) {
+        const float x = wave_min(v[64 * sg + lane]);
+        if (lane == 0) red[sg] = x;
+    }
     __syncthreads();
-    return (red[0] + red[1]) + (red[2] + red[3]);
+    const float r = fminf(fminf(red[0], red[1]), fminf(red[2], red[3]));
+    __syncthreads();
+    return r;
 }
 
-// Weights and update (Eq. 14-17 and Eq. 4) for chunk b of a step's G chunks
-// of up to 256 samples, one workgroup of 256 threads per chunk:
-//  1. S~ = S + J_C per sample; the chunk's minimum beta_b, its weights
-//     exp(-(S~ - beta_b)/lambda) and their sum Z_b;
-//  2. the chunk's weighted control sums N_b[t] = sum_k w_k u_{k,t}, thread
-//     (t, part) summing a contiguous slice of the chunk, the slices then added
-//     in order;
-//  3. the partials (beta_b, Z_b, N_b) go to the workspace; the workgroup that
-//     finishes last (an acquire-release counter, which it resets for the next
-//     launch) merges them: beta = min beta_b, scale_b = exp(-(beta_b -
-//     beta)/lambda), V+ = sum_b scale_b N_b / sum_b scale_b Z_b, then writes V
-//     (shifted when asked), the first command and, in debug mode, w_hat.
-// No workgroup waits for another, and every sum runs in a fixed order.
-// LDS (dynamic): w[256] | slice sums [parts][2T] | scale[G] | vp[2T].
-__device__ __forceinline__ void update_body(const StepConst& c, int b, int G, int parts, const float* __restrict__ S,
-                                            const float* __restrict__ cvar, const float2* __restrict__ u,
-                                            float* __restrict__ S_tilde, float* part, unsigned* counter,
-                                            float* __restrict__ V, float* __restrict__ u0,
-                                            float* __restrict__ u0_host, float* __restrict__ w_hat, float* ush,
-                                            float* red, int* is_last_sh, const GradOut* go = nullptr) {
-    int& is_last = *is_last_sh;
+// Weights and update (Eq. 14-17 and Eq. 4), in chunks of 256 samples; any
+// workgroup size that is a multiple of 64 gives the same bits.
+//  1. (update_chunk) S~ = S + J_C per sample of chunk b; the chunk's minimum
+//     beta_b, its weights exp(-(S~ - beta_b)/lambda) and their sum Z_b;
+//  2. (update_chunk) the chunk's weighted control sums N_b[t] = sum_k w_k
+//     u_{k,t}, item (t, part) summing a contiguous slice of the chunk, the
+//     slices then added in order; (beta_b, Z_b, N_b) go to part[b];
+//  3. (update_merge, run by whoever finishes the last chunk) beta = min
+//     beta_b, scale_b = exp(-(beta_b - beta)/lambda), V+ = sum_b scale_b N_b /
+//     sum_b scale_b Z_b; then V (shifted when asked), the first command and,
+//     in debug mode, w_hat; in gradient mode J, every w_hat and the list of
+//     samples of non-zero weight instead, V unchanged.
+// LDS (dynamic, ush): w[256] | slice sums [parts][2T], then for the merge
+// v[256] | scale[G] | vp[2T] (update_lds_bytes).
+template <int kB>
+__device__ __forceinline__ void update_chunk(const StepConst& c, int b, int parts, const float* __restrict__ S,
+                                             const float* __restrict__ cvar, const float2* __restrict__ u,
+                                             float* __restrict__ S_tilde, float* __restrict__ part, float* ush,
+                                             float* red) {
     const int T = c.T, K = c.K;
+    const int tid = threadIdx.x, nt = blockDim.x;
     float* wsh = ush;
     float* psh = wsh + 256;
-    const int tid = threadIdx.x;
     const int k0 = b * 256;
     const int n = min(256, K - k0);
     const int stride = 2 + 2 * T;
 
     // 1. modified costs and chunk weights
-    float st = __builtin_inff();
-    if (tid < n) {
-        const float cv = cvar[k0 + tid];
-        const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
-        st = S[k0 + tid] + jc;                             // Eq. 16
-        S_tilde[k0 + tid] = st;
+    for (int i = tid; i < 256; i += nt) {
+        float st = __builtin_inff();
+        if (i < n) {
+            const float cv = cvar[k0 + i];
+            const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
+            st = S[k0 + i] + jc;                               // Eq. 16
+            S_tilde[k0 + i] = st;
+        }
+        wsh[i] = st;
     }
-    const float beta_b = block_min_256(st, red);
-    const float w = (tid < n) ? expf(-(st - beta_b) / c.lambda) : 0.0f;
-    wsh[tid] = w;
-    const float Z_b = block_sum_256(w, red);  // also publishes wsh
+    const float beta_b = seg_min_256(wsh, red);
+    for (int i = tid; i < 256; i += nt) wsh[i] = (i < n) ? expf(-(wsh[i] - beta_b) / c.lambda) : 0.0f;
+    const float Z_b = seg_sum_256(wsh, red);  // also publishes wsh
 
     // 2. weighted control sums over slices of the chunk
     const int slice = (n + parts - 1) / parts;
-    for (int idx = tid; idx < T * parts; idx += 256) {
+    for (int idx = tid; idx < T * parts; idx += nt) {
         const int t = idx % T;
         const int pr = idx / T;
         const int ka = pr * slice, kb = min(n, ka + slice);
         const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
         int k = ka;
-        for (; k + 16 <= kb; k += 16) {  // 16 loads in flight, then the sums in order
-            float2 uu[16];
+        for (; k + kB <= kb; k += kB) {  // kB loads in flight, then the sums in order
+            float2 uu[kB];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) uu[i] = ut[k + i];
+            for (int i = 0; i < kB; ++i) uu[i] = ut[k + i];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < kB; ++i) {
                 ax = __fmaf_rn(wsh[k + i], uu[i].x, ax);
                 ay = __fmaf_rn(wsh[k + i], uu[i].y, ay);
             }
@@ -288,7 +301,7 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
     }
     __syncthreads();
     float* pb = part + (size_t)b * stride;
-    for (int j = tid; j < 2 * T; j += 256) {
+    for (int j = tid; j < 2 * T; j += nt) {
         float acc = 0.0f;
         for (int pr = 0; pr < parts; ++pr) acc += psh[(size_t)pr * 2 * T + j];
         pb[2 + j] = acc;
@@ -297,43 +310,49 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         pb[0] = beta_b;
         pb[1] = Z_b;
     }
+    __syncthreads();  // LDS free for the caller
+}
 
-    // 3. the last workgroup to finish merges every chunk.  Thread 0's
-    // device-scope release (after the barrier that orders the other threads'
-    // stores before it) publishes the chunk's partials; the last workgroup's
-    // acquire makes them visible to all its threads.
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (done == (unsigned)(G - 1));
-        if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
-
-    float* scale = psh;               // reuses the slice sums
+template <int kB>
+__device__ __forceinline__ void update_merge(const StepConst& c, int G, const float* __restrict__ part,
+                                             const float* __restrict__ S_tilde, float* __restrict__ V,
+                                             float* __restrict__ u0, float* __restrict__ u0_host,
+                                             float* __restrict__ w_hat, float* ush, float* red,
+                                             const GradOut* go = nullptr) {
+    const int T = c.T, K = c.K;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int stride = 2 + 2 * T;
+    float* vsh = ush;  // 256 per-virtual-thread values
+    float* scale = vsh + 256;
     float* vp = scale + G;
-    float bmin = __builtin_inff();
-    for (int bb = tid; bb < G; bb += 256) bmin = fminf(bmin, part[(size_t)bb * stride]);
-    const float beta = block_min_256(bmin, red);
-    float z = 0.0f;
-    for (int bb = tid; bb < G; bb += 256) {
-        const float sc = expf(-(part[(size_t)bb * stride] - beta) / c.lambda);
-        scale[bb] = sc;
-        z = __fmaf_rn(part[(size_t)bb * stride + 1], sc, z);
+
+    // virtual thread i (of 256) takes chunks i, i + 256, ...
+    for (int i = tid; i < 256; i += nt) {
+        float m = __builtin_inff();
+        for (int bb = i; bb < G; bb += 256) m = fminf(m, part[(size_t)bb * stride]);
+        vsh[i] = m;
     }
-    const float Z = block_sum_256(z, red);  // also publishes scale
+    const float beta = seg_min_256(vsh, red);
+    for (int i = tid; i < 256; i += nt) {
+        float z = 0.0f;
+        for (int bb = i; bb < G; bb += 256) {
+            const float sc = expf(-(part[(size_t)bb * stride] - beta) / c.lambda);
+            scale[bb] = sc;
+            z = __fmaf_rn(part[(size_t)bb * stride + 1], sc, z);
+        }
+        vsh[i] = z;
+    }
+    const float Z = seg_sum_256(vsh, red);  // also publishes scale
     const float invZ = 1.0f / Z;
-    for (int j = tid; j < 2 * T; j += 256) {
+    for (int j = tid; j < 2 * T; j += nt) {
         float acc = 0.0f;
         int bb = 0;
-        for (; bb + 16 <= G; bb += 16) {  // 16 loads in flight, then the sums in order
-            float pv[16];
+        for (; bb + kB <= G; bb += kB) {  // kB loads in flight, then the sums in order
+            float pv[kB];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) pv[i] = part[(size_t)(bb + i) * stride + 2 + j];
+            for (int i = 0; i < kB; ++i) pv[i] = part[(size_t)(bb + i) * stride + 2 + j];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) acc = __fmaf_rn(pv[i], scale[bb + i], acc);
+            for (int i = 0; i < kB; ++i) acc = __fmaf_rn(pv[i], scale[bb + i], acc);
         }
         for (; bb < G; ++bb) acc = __fmaf_rn(part[(size_t)bb * stride + 2 + j], scale[bb], acc);
         vp[j] = acc * invZ;
@@ -343,8 +362,9 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         // gradient mode: V stays as it is; write J = beta - lambda log(Z/K),
         // every w_hat, and the samples of non-zero weight in increasing order
         if (tid == 0) *go->J = beta - c.lambda * logf(Z / (float)K);
+        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
         int base = 0;
-        for (int k0b = 0; k0b < K; k0b += 256) {
+        for (int k0b = 0; k0b < K; k0b += nt) {
             const int k = k0b + tid;
             float wk = 0.0f;
             if (k < K) {
@@ -354,15 +374,16 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
             const int flag = (k < K) && (wk > 0.0f);
             // exclusive prefix of the flags in thread order (fixed, so the list is deterministic)
             const uint64_t ball = __builtin_amdgcn_ballot_w64(flag);
-            const int lane = tid & 63, wv = tid >> 6;
             const int in_wave = __builtin_popcountll(ball & ((1ull << lane) - 1ull));
             __syncthreads();
             if (lane == 0) red[wv] = __int_as_float(__builtin_popcountll(ball));
             __syncthreads();
-            int before = 0;
-            for (int q = 0; q < wv; ++q) before += __float_as_int(red[q]);
-            const int total = __float_as_int(red[0]) + __float_as_int(red[1]) + __float_as_int(red[2]) +
-                              __float_as_int(red[3]);
+            int before = 0, total = 0;
+            for (int q = 0; q < nw; ++q) {
+                const int cq = __float_as_int(red[q]);
+                before += (q < wv) ? cq : 0;
+                total += cq;
+            }
             if (flag) go->act_list[base + before + in_wave] = k;
             base += total;
         }
@@ -370,7 +391,7 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
         return;
     }
     const int shift = (c.flags & 2u) != 0;
-    for (int j = tid; j < 2 * T; j += 256) {
+    for (int j = tid; j < 2 * T; j += nt) {
         int src = j;
         if (shift) src = min(j + 2, 2 * T - 2 + (j & 1));
         V[j] = vp[src];
@@ -384,8 +405,107 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
                                __HIP_MEMORY_SCOPE_SYSTEM);
     }
     if (c.debug) {
-        for (int k = tid; k < K; k += 256) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
+        for (int k = tid; k < K; k += nt) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
     }
+}
+
+// Thread 0 adds one to a device-scope counter with acquire-release order
+// (after the barrier that orders the workgroup's earlier stores before it);
+// returns to every thread whether this made it reach `target`, in which case
+// the counter is reset to zero and every thread has acquired what the other
+// increments published.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned target, int* flag_sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        *flag_sh = (done == target - 1u);
+        if (*flag_sh) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const bool last = *flag_sh != 0;
+    if (last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    return last;
+}
+
+// Loads in flight per thread in the update run inside the rollout launch,
+// whose register budget is the rollout's (the separate update launch uses 16).
+constexpr int kFuseBatch = 4;
+
+// Buffers of the update run inside the rollout launch (one step in one
+// kernel), held in device memory so that they occupy no registers during the
+// rollouts.
+struct FuseArgs {
+    unsigned* chunk_ctr;  // G counters of finished contributors (zero between launches)
+    unsigned* counter;    // chunks finished (zero between launches)
+    float* S_tilde;
+    float* part;
+    float* u0;
+    float* u0_host;       // mapped host buffer, written when the step asks for the first command
+    float* w_hat;
+    int G, parts;
+};
+
+// Workgroups of a rollout launch whose samples fall in chunk b: the nominal
+// workgroups (block samples each) and the disturbed ones (spb samples each).
+__device__ __forceinline__ unsigned chunk_contributors(const StepConst& c, int b, int block) {
+    const int klo = 256 * b, khi = min(c.K, klo + 256) - 1;
+    return (unsigned)((khi / block - klo / block + 1) + (khi / c.spb - klo / c.spb + 1));
+}
+
+// After a rollout workgroup has stored its results: it counts itself in the
+// chunks its samples fall in, and for every chunk it completes runs that
+// chunk's update (its inputs S, CVaR and u are then all stored, published by
+// the other workgroups' releases); the workgroup that completes the last
+// chunk merges them.  No workgroup waits for another.
+__device__ __forceinline__ void fused_update(const StepConst& c, const FuseArgs& f, int item, const float* S,
+                                             const float* cvar, const float2* u, float* V, float* ush, float* red,
+                                             int* flag_sh, int* fin_sh) {
+    int lo, hi;
+    if (item < c.n_nom_wg) {
+        lo = item * (int)blockDim.x;
+        hi = min(c.K, lo + (int)blockDim.x);
+    } else {
+        lo = (item - c.n_nom_wg) * c.spb;
+        hi = min(c.K, lo + c.spb);
+    }
+    __syncthreads();  // the workgroup's stores precede thread 0's release; LDS free
+    if (threadIdx.x == 0) {
+        int nf = 0;
+        for (int b = lo >> 8; b <= (hi - 1) >> 8; ++b) {
+            const unsigned target = chunk_contributors(c, b, (int)blockDim.x);
+            const unsigned done =
+                __hip_atomic_fetch_add(&f.chunk_ctr[b], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (done == target - 1u) {
+                __hip_atomic_store(&f.chunk_ctr[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                fin_sh[nf++] = b;
+            }
+        }
+        fin_sh[7] = nf;
+    }
+    __syncthreads();
+    const int nf = fin_sh[7];
+    if (nf == 0) return;
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    for (int i = 0; i < nf; ++i) {
+        update_chunk<kFuseBatch>(c, fin_sh[i], f.parts, S, cvar, u, f.S_tilde, f.part, ush, red);
+        if (arrive_last(f.counter, (unsigned)f.G, flag_sh))
+            update_merge<kFuseBatch>(c, f.G, f.part, f.S_tilde, V, f.u0, c.u0_seq ? f.u0_host : nullptr, f.w_hat,
+                                     ush, red);
+    }
+}
+
+// One chunk of the update, and the merge when it is the last chunk to finish
+// (a separate launch of G workgroups, one chunk each).  No workgroup waits
+// for another, and every sum runs in a fixed order.
+__device__ __forceinline__ void update_body(const StepConst& c, int b, int G, int parts, const float* __restrict__ S,
+                                            const float* __restrict__ cvar, const float2* __restrict__ u,
+                                            float* __restrict__ S_tilde, float* part, unsigned* counter,
+                                            float* __restrict__ V, float* __restrict__ u0,
+                                            float* __restrict__ u0_host, float* __restrict__ w_hat, float* ush,
+                                            float* red, int* flag_sh, const GradOut* go = nullptr) {
+    update_chunk<16>(c, b, parts, S, cvar, u, S_tilde, part, ush, red);
+    if (!arrive_last(counter, (unsigned)G, flag_sh)) return;
+    update_merge<16>(c, G, part, S_tilde, V, u0, u0_host, w_hat, ush, red, go);
 }
 
 }  // namespace ramppi

@@ -281,6 +281,31 @@ def test_dense_obstacle_fields(n_obs, M):
     assert hits > 0.02
 
 
+@pytest.mark.parametrize("name,kw", [("c1", {}), ("c2", {}), ("p0", dict(M=128)), ("c1", dict(K=257, M=48, T=9)),
+                                     ("c1", dict(K=700, M=7, T=5, B=2.0, eta=0.3))])
+def test_one_launch_step_equals_split_update(name, kw):
+    # the step as one launch (the update run by the workgroups that finish
+    # each chunk) and as two launches give the same bits, over several calls
+    # (the chunk and merge counters reset themselves between launches)
+    p, obs, x0, _ = _world(name, **kw)
+    p = dict(p, shift=True)
+    V0 = W.random_V(p["T"], 9, scale=(1.0, 0.2))
+    a = R.Controller(p, obs, debug=True)
+    b = R.Controller(p, obs, debug=True, split_update=True)
+    Va, Vb = a.new_V(V0), b.new_V(V0)
+    for j in range(4):
+        ua = a.step(x0, Va, 3 + j)
+        ub = b.step(x0, Vb, 3 + j)
+        torch.cuda.synchronize()
+        assert np.array_equal(ua, ub)
+        assert torch.equal(Va, Vb)
+        da, db = a.debug(), b.debug()
+        for k in ("u", "S", "L", "cvar", "S_tilde", "w_hat", "u0"):
+            assert torch.equal(da[k], db[k]), (j, k)
+    a.close()
+    b.close()
+
+
 def test_shift_and_first_command():
     p, obs, x0, V0 = _world("c1", shift=True)
     g, o, rep = _run(p, obs, x0, V0, 0, shift=True)
