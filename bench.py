@@ -7,12 +7,14 @@ the first command read back every step and a host FP64 plant closing the
 loop.  Synthetic seeded inputs.  One JSON line on stdout:
 
   value        rollout-steps/s (K M T per step) over the timed steps
-  roofline     the rollout kernel: the FP32 FLOPs it executes per launch
+  roofline     the rollout kernel: the FP32 FLOPs of its rollouts per launch
                (with the broad-phase candidates counted on the device over
                the timed steps) / its average HIP-event duration on the
                step's stream, against the FP32 vector peak; the
                brute-force-equivalent rate (every obstacle tested at every
-               state) is given beside it
+               state) is given beside it.  When the whole grid is resident
+               the step is one launch whose duration also covers the update
+               (about 3 % of the FLOPs, not counted)
   cpu_baseline the FP64 oracle on a bounded sample of the same workload,
                timed on this host's cores
 
@@ -85,6 +87,37 @@ def model_bytes(p: dict, n_obs: int) -> float:
     table, write the K x T x 2 controls, S and CVaR."""
     K, T = p["K"], p["T"]
     return 8.0 * T + 16.0 * n_obs + 8.0 * K * T + 8.0 * K
+
+
+def kernel_sources_sha256() -> str:
+    """Hash of the HIP sources and the C header (the code the counters measured)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2209_12842_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
+    for path in files + [os.path.join(ROOT, "include", "ramppi.h")]:
+        h.update(os.path.basename(path).encode())
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per rollout launch from the committed counter summary
+    (profiles/k_rollout_<workload>_traffic.md): FETCH_SIZE and WRITE_SIZE,
+    each scaled by the same counter's reading for a plain copy of known size.
+    None when there is no summary or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "k_rollout_%s_traffic.md" % workload)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel sources sha256") != kernel_sources_sha256():
+        return None
+    return float(vals["fetch bytes per launch"]) + float(vals["write bytes per launch"])
 
 
 def plant_step(x, u, dt, wb, w):
@@ -207,7 +240,7 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "kernel_ms": {"rollout": roll_avg_s * 1e3, "update": upd_ms / max(n_timed, 1)},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_rollout", "executed_flops_per_launch": flops,
                      "broad_phase_candidates_per_launch": cand,
                      "brute_force_equivalent_tflops": brute_tf},
