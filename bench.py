@@ -30,6 +30,12 @@ Other legs (one JSON line each, not the default):
                   c4: K = 4096, T = 50, M = 64): evaluations per second, its
                   cost relative to a plain step, and gradient-corrected steps
                   against plain steps at equal wall time
+  --study         closed loop on the p0 oval (the paper's controller settings,
+                  0.6 m track, ten 0.1 m obstacles): RA-MPPI (A = 10) against
+                  plain MPPI (A = 0) under the same seeded plant disturbances,
+                  collisions and track-boundary violations per lap; a synthetic
+                  stand-in for the paper's collision study that shows only the
+                  direction of the effect
 """
 from __future__ import annotations
 
@@ -156,6 +162,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default=None, choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--grad", action="store_true")
+    ap.add_argument("--study", action="store_true")
+    ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-sized device buffer 3 times (a plain copy kernel of "
@@ -171,6 +179,8 @@ def main():
 
     if args.grad:
         return run_grad(args, R, torch)
+    if args.study:
+        return run_study(args, R, torch)
     if args.workload == "c5":
         return run_batch(args, R, torch)
     if args.workload is None:
@@ -452,6 +462,68 @@ def run_grad(args, R, torch):
     }
     print(json.dumps(out), flush=True)
     ctl.close()
+
+
+def run_study(args, R, torch):
+    """Closed-loop collisions of RA-MPPI and plain MPPI on the p0 oval."""
+    world = W.make_world("p0")
+    base = dict(world["params"], shift=True)
+    obs = np.asarray(world["obstacles"], dtype=np.float64)
+    a, b, hw = base["track"][2], base["track"][3], base["track"][4]
+    dt32, wb32 = float(np.float32(base["dt"])), float(np.float32(base["wheelbase"]))
+    sw = np.sqrt(np.float32(base["sigma_w"]).astype(np.float64))
+    n_steps = args.steps
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    def run(A, seed):
+        p = dict(base, A=A)
+        ctl = R.Controller(p, world["obstacles"], device=dev)
+        V = ctl.new_V()
+        w = np.random.default_rng(1000 + seed).standard_normal((n_steps, 4)) * sw
+        x = [float(v) for v in world["x0"]]
+        th_prev = math.atan2(x[1] / b, x[0] / a)
+        turned, coll, out, t0 = 0.0, 0, 0, time.perf_counter()
+        for j in range(n_steps):
+            u0 = ctl.step(x, V, (seed << 16) + j, want_u0=True)
+            x = plant_step(x, u0, dt32, wb32, w[j])
+            d2 = (obs[:, 0] - x[0]) ** 2 + (obs[:, 1] - x[1]) ** 2
+            coll += int(np.any(d2 < obs[:, 2] ** 2))
+            G = (x[0] / a) ** 2 + (x[1] / b) ** 2 - 1.0
+            e = G / math.hypot(2 * x[0] / a ** 2, 2 * x[1] / b ** 2)
+            out += int(abs(e) > hw)
+            th = math.atan2(x[1] / b, x[0] / a)
+            turned += (th - th_prev + math.pi) % (2 * math.pi) - math.pi
+            th_prev = th
+        ctl.close()
+        return dict(laps=turned / (2 * math.pi), collisions=coll, outside=out, s=time.perf_counter() - t0)
+
+    res = {A: [run(A, s) for s in range(args.seeds)] for A in (0.0, 10.0)}
+
+    def stat(rs, key):
+        v = np.array([r[key] / max(r["laps"], 1e-9) for r in rs])
+        return float(v.mean()), float(v.std(ddof=1) / math.sqrt(len(v))) if len(v) > 1 else 0.0
+
+    summary = {}
+    for A, rs in res.items():
+        name = "ra_mppi" if A > 0 else "mppi"
+        cm, cse = stat(rs, "collisions")
+        om, ose = stat(rs, "outside")
+        summary[name] = {"collision_steps_per_lap": cm, "collision_se": cse, "outside_steps_per_lap": om,
+                         "outside_se": ose, "laps_mean": float(np.mean([r["laps"] for r in rs])),
+                         "ms_per_step": 1e3 * float(np.mean([r["s"] for r in rs])) / n_steps}
+    out = {
+        "metric": "collision steps per lap (plant inside an obstacle), closed loop on the p0 oval",
+        "value": summary["ra_mppi"]["collision_steps_per_lap"], "unit": "steps/lap", "n_gpus": 1,
+        "steps": n_steps, "warmup": 0, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (p0 world, %d seeds of Gaussian plant disturbances shared by both controllers)"
+                % args.seeds,
+        "config": {"workload": "p0: K=%d T=%d M=%d lambda=%g alpha=%g C_u=%g, A=10 vs A=0, %d steps of %g s"
+                               % (base["K"], base["T"], base["M"], base["lam"], base["alpha"], base["C_u"],
+                                  n_steps, base["dt"]), "parallelism": "single GPU"},
+        "study": summary,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
