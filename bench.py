@@ -65,34 +65,28 @@ def model_flops(p: dict, n_obs: int) -> float:
     return K * M * T * (80.0 + 7.0 * n_obs) + K * T * (60.0 + 7.0 * n_obs)
 
 
-def rollout_waves(p: dict, block: int | None = None) -> int:
-    """Waves of one rollout launch (nominal and disturbed workgroups)."""
+def disturbed_waves(p: dict, block: int | None = None) -> int:
+    """Waves of the disturbed workgroups of one rollout launch (workgroups of
+    `block` threads; by default the single-controller size)."""
     K, M = p["K"], p["M"]
     spb = 1 if M >= 256 else 256 // M
     if block is None:
         block = (spb * M + 63) // 64 * 64
-    n_nom = (K + block - 1) // block
-    n_dist = (K + spb - 1) // spb
-    return (n_nom + n_dist) * (block // 64)
+    return (K + spb - 1) // spb * (block // 64)
 
 
 def executed_flops(p: dict, n_obs: int, candidates: float, block: int | None = None) -> float:
-    """FP32 FLOPs the culled rollout kernel executes in one launch (FMA = 2):
-    80 per disturbed and 60 per nominal state step for dynamics, noise and
-    the smooth costs; per wave, state step and table slot (groups of 64) 17
-    for the broad-phase box test; 5 per lane for each exact test of a
-    broad-phase candidate (`candidates` counted on the device, per wave)."""
+    """FP32 FLOPs the rollout kernel executes in one launch (FMA = 2):
+    80 per disturbed state step for dynamics, noise and the smooth costs;
+    per disturbed wave, state step and table slot (groups of 64) 17 for the
+    broad-phase box test, and 5 per lane for each exact test of a candidate
+    (`candidates` counted on the device, per wave); 60 + 7 per padded
+    obstacle (every obstacle tested) per nominal state step."""
     K, T, M = p["K"], p["T"], p["M"]
     n_grp = (n_obs + 63) // 64
-    return (80.0 * K * M * T + 60.0 * K * T + 17.0 * 64 * n_grp * T * rollout_waves(p, block)
-            + 5.0 * 64 * candidates)
-
-
-def model_bytes(p: dict, n_obs: int) -> float:
-    """Algorithmic HBM bytes of one rollout launch: read V and the obstacle
-    table, write the K x T x 2 controls, S and CVaR."""
-    K, T = p["K"], p["T"]
-    return 8.0 * T + 16.0 * n_obs + 8.0 * K * T + 8.0 * K
+    n_tab = (n_obs + 7) // 8 * 8
+    return (80.0 * K * M * T + 17.0 * 64 * n_grp * T * disturbed_waves(p, block) + 5.0 * 64 * candidates
+            + (60.0 + 7.0 * n_tab) * K * T)
 
 
 def kernel_sources_sha256() -> str:

@@ -141,6 +141,15 @@ __device__ __forceinline__ void bicycle_step(State& s, float da, float kappa, fl
     s.v = s.v + da;
 }
 
+// tan of a steering angle (|d| < pi/2; the control box keeps it well inside):
+// the hardware sine and cosine of d in revolutions and one reciprocal.  Used
+// by every rollout (nominal, disturbed, and the gradient's recomputation), so
+// all of them see the same dynamics.
+__device__ __forceinline__ float tan_steer(float d) {
+    const float r = d * 0.159154943091895335769f;
+    return __builtin_amdgcn_sinf(r) * __builtin_amdgcn_rcpf(__builtin_amdgcn_cosf(r));
+}
+
 // Track and speed terms of q: c_dev e^2 + c_v (v - v_ref)^2 [+ c_bdry mu_bdry].
 __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s) {
     const float X = s.x + c.tox;

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
     for (int t = 0; t < T; ++t) {
         a.states[(size_t)t * a.stride + l] = make_float4(s.x, s.y, s.psi, s.v);
         const float2 uu = a.u[(size_t)t * K + k];
-        bicycle_step(s, c.dt * uu.x, tanf(uu.y) * c.inv_wheelbase, c.dt);
+        bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
         if (m >= 0 && t + 1 < T) {
             const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
             const float4 w = disturbance<kNoise>(c, r);
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
         const float4 xv = a.states[(size_t)t * a.stride + l];
         const State x{xv.x, xv.y, xv.z, xv.w};
         const float2 uu = a.u[(size_t)t * K + k];
-        const float tn = tanf(uu.y);
+        const float tn = tan_steer(uu.y);
         float r = x.psi * 0.159154943091895335769f;
         r = r - rintf(r);
         const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);

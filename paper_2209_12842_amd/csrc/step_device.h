@@ -108,8 +108,11 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     if (item < c.n_nom_wg) {
         // ---- nominal rollouts: one lane per sample; lanes past K repeat
         // the last sample (the obstacle test works on whole waves) and write
-        // nothing ----
-        __syncthreads();  // otab staged
+        // nothing.  V is staged into LDS (the controls' region, unused here),
+        // so that no step waits for a global load ----
+        float* vsh = reinterpret_cast<float*>(ctl);  // 2T floats <= 2 spb T
+        for (int i = tid; i < 2 * T; i += blockDim.x) vsh[i] = V[i];
+        __syncthreads();  // otab and V staged
         const int k = item * blockDim.x + tid;
         const bool act = k < c.K;
         const int kc = act ? k : c.K - 1;
@@ -117,15 +120,15 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
         for (int t = 0; t < T; ++t) {
-            const float2 u = sample_control(c, V, kc, t);
+            const float2 u = sample_control(c, vsh, kc, t);
             if (act) u_out[(size_t)t * c.K + k] = u;
             acc += smooth_cost(c, s);
             if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y, n_cand);
             if (c.use_ctrl) {
-                const float term = __fmaf_rn(V[2 * t] * c.inv_var0, u.x, V[2 * t + 1] * c.inv_var1 * u.y);
+                const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
                 ctrl = __fmaf_rn(c.gamma, term, ctrl);
             }
-            bicycle_step(s, c.dt * u.x, tanf(u.y) * c.inv_wheelbase, c.dt);
+            bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
         }
         float S = __fmaf_rn(c.c_obs, (float)cnt, acc);
         if (c.use_ctrl) S += ctrl;
@@ -145,7 +148,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         float2 cu = make_float2(0.0f, 0.0f);
         if (kk < c.K) {
             const float2 u = sample_control(c, V, kk, t);
-            cu = make_float2(c.dt * u.x, tanf(u.y) * c.inv_wheelbase);
+            cu = make_float2(c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase);
         }
         ctl[idx] = cu;
     }
