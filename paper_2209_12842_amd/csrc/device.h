@@ -138,7 +138,13 @@ __device__ __forceinline__ void bicycle_step(State& s, float da, float kappa, fl
     s.x = __fmaf_rn(dv, cs, s.x);
     s.y = __fmaf_rn(dv, sn, s.y);
     s.psi = __fmaf_rn(dv, kappa, s.psi);
-    s.v = s.v + da;
+    {
+        // da is the rounded product dt a in every rollout (nominal, disturbed
+        // and the gradient's recomputation): never fused with the multiply
+        // that produced it, so all of them see the same dynamics
+#pragma clang fp contract(off)
+        s.v = s.v + da;
+    }
 }
 
 // tan of a steering angle (|d| < pi/2; the control box keeps it well inside):

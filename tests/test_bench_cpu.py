@@ -1,0 +1,33 @@
+"""Host logic of the benchmark: the FLOP models, the traffic record and its
+guard against a changed kernel (CPU only)."""
+import bench
+from paper_2209_12842_amd import workloads as W
+
+
+def test_brute_force_model_matches_the_survey_counts():
+    # 80 + 7 n_obs per disturbed and 60 + 7 n_obs per nominal state step
+    p = W.make_world("c2")["params"]
+    assert bench.model_flops(p, 50) == 2048 * 64 * 50 * 430 + 2048 * 50 * 410
+    p3 = W.make_world("c3")["params"]
+    assert abs(bench.model_flops(p3, 200) - 3.13e11) / 3.13e11 < 0.01
+
+
+def test_executed_model_counts_waves_groups_and_candidates():
+    p = dict(K=256, T=10, M=64)
+    # 256 samples of 64 draws: 4 samples per workgroup of 256 threads, 64 workgroups of 4 waves
+    assert bench.disturbed_waves(p) == 256
+    base = bench.executed_flops(p, 10, 0.0)
+    assert base == 80.0 * 256 * 64 * 10 + 17.0 * 64 * 1 * 10 * 256 + (60.0 + 7.0 * 16) * 256 * 10
+    assert bench.executed_flops(p, 10, 3.0) - base == 5.0 * 64 * 3.0
+    # the batched path runs workgroups of 256 threads whatever M is
+    q = dict(K=256, T=10, M=129)
+    assert bench.disturbed_waves(q) == 256 * 3 and bench.disturbed_waves(q, block=256) == 256 * 4
+
+
+def test_traffic_record_is_used_only_for_the_kernel_it_measured(monkeypatch):
+    for wl in ("c2", "c3"):
+        t = bench.measured_traffic(wl)
+        assert t is None or t > 0
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
+    assert bench.measured_traffic("c2") is None and bench.measured_traffic("c3") is None
+    assert bench.measured_traffic("c1") is None  # nothing measured

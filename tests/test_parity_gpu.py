@@ -106,10 +106,10 @@ def _world(name, **kw):
     return w["params"], w["obstacles"], w["x0"], w["V0"]
 
 
-def _run(p, obs, x0, V0, step_idx, shift=False, strict=True, allow_zero=False):
-    _log("step %s K=%d T=%d M=%d n_obs=%d idx=%d" % (p.get("config_id"), p["K"], p["T"], p["M"], len(obs),
-                                                   step_idx))
-    ctl = R.Controller(p, obs, debug=True, allow_zero_noise=allow_zero)
+def _run(p, obs, x0, V0, step_idx, shift=False, strict=True, allow_zero=False, split=False):
+    _log("step %s K=%d T=%d M=%d n_obs=%d idx=%d split=%d" % (p.get("config_id"), p["K"], p["T"], p["M"], len(obs),
+                                                            step_idx, split))
+    ctl = R.Controller(p, obs, debug=True, allow_zero_noise=allow_zero, split_update=split)
     g = gpu_step(ctl, x0, V0, step_idx)
     o = oracle.step(p, obs, x0, V0, step_idx)
     rep = check_step(p, g, o, shift=shift, strict_e2e=strict)
@@ -244,14 +244,15 @@ def test_plain_mppi_ignores_disturbances_on_device():
                                 dict(K=20, M=300, T=6), dict(K=5, M=1024, T=4), dict(K=300, M=64, T=3, n_obs=0),
                                 dict(K=64, M=16, T=9, eta=0.5, B=3.0, C_u=60.0, lam=20.0),
                                 dict(K=600, M=64, T=300, lam=50.0)])
-def test_edge_shapes(kw):
+@pytest.mark.parametrize("split", [False, True], ids=["one-launch", "split"])
+def test_edge_shapes(kw, split):
     kw = dict(kw)
     n_obs = kw.pop("n_obs", None)
     p, obs, x0, _ = _world("c1", **kw)
     if n_obs is not None:
         obs = obs[:n_obs]
     V0 = W.random_V(p["T"], 3, scale=(1.0, 0.2))
-    _run(p, obs, x0, V0, 1)
+    _run(p, obs, x0, V0, 1, split=split)
 
 
 def _dense_obstacles(n, seed, x0, r=(0.1, 0.5)):
