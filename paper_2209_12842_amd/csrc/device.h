@@ -28,6 +28,14 @@ constexpr uint32_t kCtrlWord = 0xFFFFFFFFu;
 // multipliers (full 64-bit products); the new counter is
 // (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key
 // then advances by the two Weyl constants.
+// a ^ b ^ k in one instruction (gfx950's three-input bitwise operation with
+// the truth table of XOR3); k is the key word, the same in every lane.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -36,8 +44,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         const uint64_t p1 = (uint64_t)c2 * kPhiloxM1;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        const uint32_t n0 = xor3_key(hi1, c1, k0);
+        const uint32_t n2 = xor3_key(hi0, c3, k1);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
