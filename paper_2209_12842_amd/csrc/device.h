@@ -38,8 +38,22 @@ __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
 
 __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
+    {
+        // first round in plain C: counter words that are the same in every
+        // lane (the time step, the call index) then stay on the scalar unit
+        const uint64_t p0 = (uint64_t)c0 * kPhiloxM0;
+        const uint64_t p1 = (uint64_t)c2 * kPhiloxM1;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
 #pragma unroll
-    for (int r = 0; r < 10; ++r) {
+    for (int r = 1; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)c0 * kPhiloxM0;  // one v_mad_u64_u32 each
         const uint64_t p1 = (uint64_t)c2 * kPhiloxM1;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
@@ -56,9 +70,12 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
-// uint32 -> (0, 1): ((r >> 9) + 1/2) 2^-23, exact in FP32.
+// uint32 -> (0, 1): ((r >> 9) + 1/2) 2^-23, exact in FP32.  Built as the
+// float 1 + (r >> 9) 2^-23 (exponent bits 0x7F over the top 23 bits of r, one
+// funnel shift) minus (1 - 2^-24), a subtraction that is exact (both lie in
+// [1/2, 2] of each other and the result needs 24 significant bits).
 __device__ __forceinline__ float uniform01(uint32_t r) {
-    return __fmaf_rn((float)(r >> 9), 0x1p-23f, 0x1p-24f);
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
 }
 
 // Two standard normals from two uniforms (Box-Muller).  The hardware
@@ -190,9 +207,9 @@ __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s)
 // two FMAs on rho = |p|^2 and one compare.
 
 // Wave-wide maximum of a 32-bit unsigned value over all 64 lanes (every lane
-// active): rows of 16 lanes reduce with DPP lane permutations, the four row
-// results are read into SGPRs and combined on the scalar unit.  The result
-// is wave-uniform.  Non-negative floats order like their bit patterns, so it
+// active): rows of 16 lanes reduce with DPP lane permutations, row broadcasts
+// carry the row results up to the last lane, which is read into an SGPR.
+// The result is wave-uniform.  Non-negative floats order like their bit patterns, so it
 // also serves for the maximum of |x|.
 template <int kCtrl>
 __device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v) {
@@ -200,16 +217,22 @@ __device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v) {
     return v > o ? v : o;
 }
 
+// Rows 1 and 3 (row_bcast:15), then rows 2 and 3 (row_bcast:31), take in
+// the last lane of the row before; other rows keep their values.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_max_rows_u32(uint32_t v) {
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kCtrl, kRowMask, 0xF, false);
+    return v > o ? v : o;
+}
+
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     v = dpp_max_u32<0xB1>(v);   // quad_perm [1,0,3,2]
     v = dpp_max_u32<0x4E>(v);   // quad_perm [2,3,0,1]
     v = dpp_max_u32<0x141>(v);  // row_half_mirror
-    v = dpp_max_u32<0x140>(v);  // row_mirror
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
-    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
-    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return max(max(a, b), max(c, d));
+    v = dpp_max_u32<0x140>(v);  // row_mirror: every lane holds its row's maximum
+    v = dpp_max_rows_u32<0x142, 0xA>(v);  // row_bcast:15
+    v = dpp_max_rows_u32<0x143, 0xC>(v);  // row_bcast:31: lane 63 holds the wave's maximum
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ float lane_f32(float v, int lane) {
