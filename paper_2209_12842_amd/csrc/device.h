@@ -253,9 +253,26 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
 // times, so a disc that is not a candidate fails the exact test in every
 // lane.  Narrow phase: the exact test of the candidates, their entries
 // broadcast from lane j.  Every lane of the wave must be active.  n_cand
-// counts the candidates (wave-uniform).
-__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float px, float py,
-                                                    int& n_cand) {
+// counts the candidates (wave-uniform).  The caller holds lane j's entry of
+// the first group in registers (e0, read once per rollout: the table does not
+// change within a step); later groups are read from LDS at every call.
+__device__ __forceinline__ void cull_group(const float4 e, float x0, float x1, float y0, float y1, float p2, float px,
+                                           float py, float rho, int& cnt, int& n_cand) {
+    const float cx = -0.5f * e.x, cy = -0.5f * e.y;
+    const float dx = fmaxf(fmaxf(x0 - cx, cx - x1), 0.0f);
+    const float dy = fmaxf(fmaxf(y0 - cy, cy - y1), 0.0f);
+    uint64_t cand = __builtin_amdgcn_ballot_w64(__fmaf_rn(dx, dx, dy * dy) < e.w + p2);
+    while (cand) {
+        const int j = __builtin_ctzll(cand);
+        cand &= cand - 1;
+        ++n_cand;
+        const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
+        cnt += (__fmaf_rn(a, px, __fmaf_rn(b, py, rho)) < z) ? 1 : 0;
+    }
+}
+
+__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float4 e0, float px,
+                                                    float py, int& n_cand) {
     const float xc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px)));
     const float yc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py)));
     const float rx = __uint_as_float(wave_max_u32(__float_as_uint(fabsf(px - xc))));
@@ -266,20 +283,9 @@ __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ o
     const float rho = __fmaf_rn(px, px, py * py);
     const int lane = threadIdx.x & 63;
     int cnt = 0;
-    for (int g = 0; g < n_grp; ++g) {
-        const float4 e = otab[g * 64 + lane];
-        const float cx = -0.5f * e.x, cy = -0.5f * e.y;
-        const float dx = fmaxf(fmaxf(x0 - cx, cx - x1), 0.0f);
-        const float dy = fmaxf(fmaxf(y0 - cy, cy - y1), 0.0f);
-        uint64_t cand = __builtin_amdgcn_ballot_w64(__fmaf_rn(dx, dx, dy * dy) < e.w + p2);
-        while (cand) {
-            const int j = __builtin_ctzll(cand);
-            cand &= cand - 1;
-            ++n_cand;
-            const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
-            cnt += (__fmaf_rn(a, px, __fmaf_rn(b, py, rho)) < z) ? 1 : 0;
-        }
-    }
+    cull_group(e0, x0, x1, y0, y1, p2, px, py, rho, cnt, n_cand);
+    for (int g = 1; g < n_grp; ++g)
+        cull_group(otab[g * 64 + lane], x0, x1, y0, y1, p2, px, py, rho, cnt, n_cand);
     return cnt;
 }
 

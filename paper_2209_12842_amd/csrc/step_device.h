@@ -116,6 +116,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         const int k = item * blockDim.x + tid;
         const bool act = k < c.K;
         const int kc = act ? k : c.K - 1;
+        const float4 e0 = n_grp > 0 ? otab[tid & 63] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
@@ -123,7 +124,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
             const float2 u = sample_control(c, vsh, kc, t);
             if (act) u_out[(size_t)t * c.K + k] = u;
             acc += smooth_cost(c, s);
-            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y, n_cand);
+            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, e0, s.x, s.y, n_cand);
             if (c.use_ctrl) {
                 const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
                 ctrl = __fmaf_rn(c.gamma, term, ctrl);
@@ -164,12 +165,13 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         // lanes past the workgroup's last sample repeat its controls, and the
         // results of inactive lanes are dropped
         const float2* ck = ctl + min(sl, spb - 1) * T;
+        const float4 e0 = n_grp > 0 ? otab[tid & 63] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f;
         int cnt = 0;
         for (int t = 0; t < T; ++t) {
             acc += smooth_cost(c, s);
-            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, s.x, s.y, n_cand);
+            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, e0, s.x, s.y, n_cand);
             if (t + 1 < T) {  // the last draw cannot reach the risk cost
                 const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
                 const float4 w = disturbance<kNoise>(c, r);
@@ -294,10 +296,20 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
                 ay = __fmaf_rn(wsh[k + i], uu[i].y, ay);
             }
         }
-        for (; k < kb; ++k) {
-            const float2 uu = ut[k];
-            ax = __fmaf_rn(wsh[k], uu.x, ax);
-            ay = __fmaf_rn(wsh[k], uu.y, ay);
+        if (k < kb) {  // the rest in one more round; padding terms are 0 * 0 and leave the sums as they are
+            float2 uu[kB];
+            float ww[kB];
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const bool in = k + i < kb;
+                uu[i] = in ? ut[k + i] : make_float2(0.0f, 0.0f);
+                ww[i] = in ? wsh[k + i] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                ax = __fmaf_rn(ww[i], uu[i].x, ax);
+                ay = __fmaf_rn(ww[i], uu[i].y, ay);
+            }
         }
         psh[(size_t)pr * 2 * T + 2 * t] = ax;
         psh[(size_t)pr * 2 * T + 2 * t + 1] = ay;
@@ -357,7 +369,17 @@ __device__ __forceinline__ void update_merge(const StepConst& c, int G, const fl
 #pragma unroll
             for (int i = 0; i < kB; ++i) acc = __fmaf_rn(pv[i], scale[bb + i], acc);
         }
-        for (; bb < G; ++bb) acc = __fmaf_rn(part[(size_t)bb * stride + 2 + j], scale[bb], acc);
+        if (bb < G) {  // the rest in one more round (padding terms 0 * 0)
+            float pv[kB], sv[kB];
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const bool in = bb + i < G;
+                pv[i] = in ? part[(size_t)(bb + i) * stride + 2 + j] : 0.0f;
+                sv[i] = in ? scale[bb + i] : 0.0f;
+            }
+#pragma unroll
+            for (int i = 0; i < kB; ++i) acc = __fmaf_rn(pv[i], sv[i], acc);
+        }
         vp[j] = acc * invZ;
     }
     __syncthreads();
