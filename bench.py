@@ -75,17 +75,26 @@ def disturbed_waves(p: dict, block: int | None = None) -> int:
     return (K + spb - 1) // spb * (block // 64)
 
 
+# Time steps whose points share one broad-phase box in the rollout kernel
+# (kCullSteps of the device code; a CPU test keeps the two equal).
+CULL_STEPS = 6
+
+
 def executed_flops(p: dict, n_obs: int, candidates: float, block: int | None = None) -> float:
     """FP32 FLOPs the rollout kernel executes in one launch (FMA = 2):
     80 per disturbed state step for dynamics, noise and the smooth costs;
-    per disturbed wave, state step and table slot (groups of 64) 17 for the
-    broad-phase box test, and 5 per lane for each exact test of a candidate
-    (`candidates` counted on the device, per wave); 60 + 7 per padded
-    obstacle (every obstacle tested) per nominal state step."""
+    per disturbed lane 4 per state step for the extent of the broad-phase
+    box, and 17 per box (one per CULL_STEPS steps) and table slot (groups of
+    64) for the box test; 5 per lane for each exact test of a (state step,
+    candidate disc) pair (`candidates` counted on the device, per wave);
+    60 + 7 per padded obstacle (every obstacle tested) per nominal state
+    step."""
     K, T, M = p["K"], p["T"], p["M"]
     n_grp = (n_obs + 63) // 64
     n_tab = (n_obs + 7) // 8 * 8
-    return (80.0 * K * M * T + 17.0 * 64 * n_grp * T * disturbed_waves(p, block) + 5.0 * 64 * candidates
+    boxes = -(-T // CULL_STEPS)
+    lanes = 64 * disturbed_waves(p, block)
+    return (80.0 * K * M * T + (4.0 * T + 17.0 * n_grp * boxes) * lanes + 5.0 * 64 * candidates
             + (60.0 + 7.0 * n_tab) * K * T)
 
 

@@ -263,7 +263,8 @@ class Controller:
         return r.value, u.value, n.value
 
     def timing_candidates(self) -> int:
-        """Broad-phase obstacle candidates of the steps timed since the last call."""
+        """Exact obstacle tests (wave, state step, obstacle) that passed the broad phase, over the steps
+        timed since the last call."""
         n = ctypes.c_uint64()
         check(lib().mppi_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(n)))
         return n.value
@@ -390,7 +391,8 @@ class Batch:
         return r.value, u.value, n.value
 
     def timing_candidates(self) -> int:
-        """Broad-phase obstacle candidates of the steps timed since the last call."""
+        """Exact obstacle tests (wave, state step, obstacle) that passed the broad phase, over the steps
+        timed since the last call."""
         n = ctypes.c_uint64()
         check(lib().mppi_batch_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)),
                                                  ctypes.byref(n)))

@@ -239,53 +239,74 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
-// Number of obstacle discs strictly containing the point, for a wave whose
-// points lie close together (the M draws of one sample).  Broad phase: a box
-// around the wave's points, [xc - Rx, xc + Rx] x [yc - Ry, yc + Ry] with
-// (xc, yc) the first lane's point and Rx, Ry the largest distances of the
-// lanes' points from it along x and y, against every disc, lane j testing
-// entry 64 g + j of the table staged in LDS (otab, n_grp groups of 64):
-// d2 = squared distance from the disc centre to the box, candidate iff
+// Number of hits of S consecutive points of a rollout (S time steps; only
+// the first n count) on the obstacle discs (a point is inside a disc iff
+// strictly closer to its centre than r), for a wave whose points lie close
+// together (the M draws of one sample).  Broad phase: a box around the
+// wave's points of all S steps, [xc - Rx, xc + Rx] x [yc - Ry, yc + Ry] with
+// (xc, yc) the first lane's first point and Rx, Ry the largest distances of
+// the lanes' points from it along x and y, against every disc, lane j
+// testing entry 64 g + j of the table staged in LDS (otab, n_grp groups of
+// 64): d2 = squared distance from the disc centre to the box, candidate iff
 // d2 < q + 2^-15 P^2, where P^2 = (|xc| + Rx)^2 + (|yc| + Ry)^2 bounds |p|^2
 // over the box.  The margin exceeds the rounding error of both this test and
 // the exact test (each a few units in the last place of r^2 + |c|^2 + |p|^2,
 // the box edges a few units in the last place of P) by more than twenty
-// times, so a disc that is not a candidate fails the exact test in every
-// lane.  Narrow phase: the exact test of the candidates, their entries
-// broadcast from lane j.  Every lane of the wave must be active.  n_cand
-// counts the candidates (wave-uniform).  The caller holds lane j's entry of
-// the first group in registers (e0, read once per rollout: the table does not
-// change within a step); later groups are read from LDS at every call.
-__device__ __forceinline__ void cull_group(const float4 e, float x0, float x1, float y0, float y1, float p2, float px,
-                                           float py, float rho, int& cnt, int& n_cand) {
+// times, so a disc that is not a candidate fails the exact test at every
+// point of every lane.  Narrow phase: the exact test of each candidate at
+// the S points, its entry broadcast from lane j.  One box serves S steps,
+// which divides the cost of the box and the group tests by S; the count is
+// an integer, so the grouping leaves it exact.  Every lane of the wave must
+// be active.  n_cand counts the exact tests per lane (candidates times
+// points, wave-uniform).  The caller holds
+// lane j's entry of the first group in registers (e0, read once per
+// rollout: the table does not change within a step); later groups are read
+// from LDS at every call.
+template <int S>
+__device__ __forceinline__ void cull_group(const float4 e, float bx0, float bx1, float by0, float by1, float p2,
+                                           const float (&px)[S], const float (&py)[S], const float (&rho)[S], int n,
+                                           int& cnt, int& n_cand) {
     const float cx = -0.5f * e.x, cy = -0.5f * e.y;
-    const float dx = fmaxf(fmaxf(x0 - cx, cx - x1), 0.0f);
-    const float dy = fmaxf(fmaxf(y0 - cy, cy - y1), 0.0f);
+    const float dx = fmaxf(fmaxf(bx0 - cx, cx - bx1), 0.0f);
+    const float dy = fmaxf(fmaxf(by0 - cy, cy - by1), 0.0f);
     uint64_t cand = __builtin_amdgcn_ballot_w64(__fmaf_rn(dx, dx, dy * dy) < e.w + p2);
     while (cand) {
         const int j = __builtin_ctzll(cand);
         cand &= cand - 1;
-        ++n_cand;
+        n_cand += n;
         const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
-        cnt += (__fmaf_rn(a, px, __fmaf_rn(b, py, rho)) < z) ? 1 : 0;
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+            if (u < n) cnt += (__fmaf_rn(a, px[u], __fmaf_rn(b, py[u], rho[u])) < z) ? 1 : 0;
     }
 }
 
-__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float4 e0, float px,
-                                                    float py, int& n_cand) {
-    const float xc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px)));
-    const float yc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py)));
-    const float rx = __uint_as_float(wave_max_u32(__float_as_uint(fabsf(px - xc))));
-    const float ry = __uint_as_float(wave_max_u32(__float_as_uint(fabsf(py - yc))));
-    const float x0 = xc - rx, x1 = xc + rx, y0 = yc - ry, y1 = yc + ry;
+// px, py: the S points (entries past n repeat a valid point).
+template <int S>
+__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float4 e0,
+                                                    const float (&px)[S], const float (&py)[S], int n, int& n_cand) {
+    const float xc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px[0])));
+    const float yc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py[0])));
+    float mx = fabsf(px[0] - xc), my = fabsf(py[0] - yc);
+    float rho[S];
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        if (u > 0) {
+            mx = fmaxf(mx, fabsf(px[u] - xc));
+            my = fmaxf(my, fabsf(py[u] - yc));
+        }
+        rho[u] = __fmaf_rn(px[u], px[u], py[u] * py[u]);
+    }
+    const float rx = __uint_as_float(wave_max_u32(__float_as_uint(mx)));
+    const float ry = __uint_as_float(wave_max_u32(__float_as_uint(my)));
+    const float bx0 = xc - rx, bx1 = xc + rx, by0 = yc - ry, by1 = yc + ry;
     const float ax = fabsf(xc) + rx, ay = fabsf(yc) + ry;
     const float p2 = 3.0517578125e-05f * __fmaf_rn(ax, ax, ay * ay);  // 2^-15 P^2
-    const float rho = __fmaf_rn(px, px, py * py);
     const int lane = threadIdx.x & 63;
     int cnt = 0;
-    cull_group(e0, x0, x1, y0, y1, p2, px, py, rho, cnt, n_cand);
+    cull_group<S>(e0, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
     for (int g = 1; g < n_grp; ++g)
-        cull_group(otab[g * 64 + lane], x0, x1, y0, y1, p2, px, py, rho, cnt, n_cand);
+        cull_group<S>(otab[g * 64 + lane], bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
     return cnt;
 }
 
@@ -338,6 +359,50 @@ __device__ __forceinline__ int tail_rank_scatter(const float* vals, float* tail,
     }
     if (rank < n_tail) tail[rank] = v;
     return rank;
+}
+
+// Value of lane (lane ^ j) of the wave, j a power of two below 64, every
+// lane active: DPP quad permutations for 1 and 2, a rotation of the 16-lane
+// row by 8 for 8, the swizzle unit's xor mode (within 32 lanes) for 4 and 16,
+// and a backward permute through the LDS crossbar for 32.
+template <int kJ>
+__device__ __forceinline__ int lane_xor(int v) {
+    if constexpr (kJ == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (kJ == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (kJ == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);
+    else if constexpr (kJ == 4 || kJ == 16) return __builtin_amdgcn_ds_swizzle(v, (kJ << 10) | 0x1F);
+    else return __builtin_amdgcn_ds_bpermute((int)(((threadIdx.x & 63) ^ 32u) << 2), v);
+}
+
+// One compare-exchange of a bitonic network whose order puts larger values
+// first and equal values by smaller index: lane i (position i in its
+// segment) pairs with i ^ j; in merge blocks of size k it keeps the earlier
+// of the two when it is the lower lane of an ascending block or the upper
+// lane of a descending one, else the later.
+__device__ __forceinline__ void bitonic_cx(float& v, int& id, float pv, int pid, int i, int j, int k) {
+    const bool mine_first = (v > pv) || (v == pv && id < pid);
+    const bool take_first = ((i & j) == 0) == ((i & k) == 0);
+    if (take_first != mine_first) {
+        v = pv;
+        id = pid;
+    }
+}
+
+template <int kJ>
+__device__ __forceinline__ void bitonic_cx_lanes(float& v, int& id, int i, int k) {
+    const float pv = __int_as_float(lane_xor<kJ>(__float_as_int(v)));
+    const int pid = lane_xor<kJ>(id);
+    bitonic_cx(v, id, pv, pid, i, kJ, k);
+}
+
+// In-wave stages (j < 64) of merge block k of the bitonic sort.
+__device__ __forceinline__ void bitonic_wave_stages(float& v, int& id, int i, int k) {
+    if (k > 32) bitonic_cx_lanes<32>(v, id, i, k);
+    if (k > 16) bitonic_cx_lanes<16>(v, id, i, k);
+    if (k > 8) bitonic_cx_lanes<8>(v, id, i, k);
+    if (k > 4) bitonic_cx_lanes<4>(v, id, i, k);
+    if (k > 2) bitonic_cx_lanes<2>(v, id, i, k);
+    bitonic_cx_lanes<1>(v, id, i, k);
 }
 
 __device__ __forceinline__ float tail_sum(const float* tail, int n_tail) {

@@ -50,11 +50,25 @@ __host__ __device__ __forceinline__ int rollout_n_grp(int n_obs) { return (n_obs
 // Slots of the broad-phase candidate counters (wave w of item i adds to slot
 // (16 i + w) mod kWorkSlots, spreading the atomics).
 constexpr int kWorkSlots = 256;
+// Time steps whose points share one broad-phase box (obstacle_hits_culled):
+// a longer run divides the box and group tests over more steps but widens
+// the box by the distance travelled; 6 gave the shortest steps on the 50- and
+// 200-obstacle tracks (horizons 50 and 100).
+constexpr int kCullSteps = 6;
 // Scal, Max and Average of Algorithm 1 for the spb samples of a workgroup.
 // vals holds the raw risk costs (thread tid owns slot tid for tid < spb * M);
-// returns the CVaR in the m == 0 lane of each sample.
+// returns the CVaR in the m == 0 lane of each sample.  The descending order
+// of a sample's M costs (equal costs by smaller draw index) comes from a
+// bitonic sort in registers when M is a power of two and the workgroup is
+// exactly spb * M lanes (stages within a wave through lane exchanges, wider
+// ones through LDS), otherwise from counting each cost's rank in LDS.  Either
+// way the n_tail largest land in tail[0..n_tail-1] in that order and are
+// summed in it, so both give the same bits.  pos_out / id_out receive one
+// (position, draw index) pair of the sorted order per lane; together the
+// lanes of a sample cover every draw once.
 __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* means, int spb, int M,
-                                               int n_tail, int scale_risk, float B, int* rank_out = nullptr) {
+                                               int n_tail, int scale_risk, float B, int* pos_out = nullptr,
+                                               int* id_out = nullptr) {
     const int tid = threadIdx.x;
     const int sl = tid / M;
     const int m = tid - sl * M;
@@ -73,9 +87,28 @@ __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* 
         }
         __syncthreads();
     }
-    if (own) {
+    if ((M & (M - 1)) == 0 && (int)blockDim.x == spb * M) {
+        float v = vals[tid];  // every lane owns a slot
+        int id = m;
+        for (int k = 2; k <= M; k <<= 1) {
+            for (int j = k >> 1; j >= 64; j >>= 1) {  // partner in another wave
+                int* ids = reinterpret_cast<int*>(tail);
+                __syncthreads();
+                vals[tid] = v;
+                ids[tid] = id;
+                __syncthreads();
+                bitonic_cx(v, id, vals[tid ^ j], ids[tid ^ j], m, j, k);
+            }
+            bitonic_wave_stages(v, id, m, k);
+        }
+        __syncthreads();  // tail free again
+        if (m < n_tail) tail[tid] = v;
+        if (pos_out) *pos_out = m;
+        if (id_out) *id_out = id;
+    } else if (own) {
         const int rank = tail_rank_scatter(vals + sl * M, tail + sl * M, M, m, n_tail);
-        if (rank_out) *rank_out = rank;
+        if (pos_out) *pos_out = rank;
+        if (id_out) *id_out = m;
     }
     __syncthreads();
     float cv = 0.0f;
@@ -103,7 +136,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     const int n_grp = rollout_n_grp(c.n_obs);
     float4* otab = reinterpret_cast<float4*>(reinterpret_cast<float*>(smem) + rollout_otab_offset(spb, T, M));
     for (int i = tid; i < n_grp * 64; i += blockDim.x) otab[i] = obstacle_entry(obs, c.n_obs, i, c.fx, c.fy);
-    int n_cand = 0;  // broad-phase candidates of this wave (wave-uniform)
+    int n_cand = 0;  // exact obstacle tests (state step, obstacle) of this wave (wave-uniform)
 
     if (item < c.n_nom_wg) {
         // ---- nominal rollouts: one lane per sample; lanes past K repeat
@@ -120,16 +153,30 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
-        for (int t = 0; t < T; ++t) {
-            const float2 u = sample_control(c, vsh, kc, t);
-            if (act) u_out[(size_t)t * c.K + k] = u;
-            acc += smooth_cost(c, s);
-            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, e0, s.x, s.y, n_cand);
-            if (c.use_ctrl) {
-                const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
-                ctrl = __fmaf_rn(c.gamma, term, ctrl);
+        for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points
+            float px[kCullSteps], py[kCullSteps];
+            int n = 0;
+#pragma unroll
+            for (int i = 0; i < kCullSteps; ++i) {
+                const int t = t0 + i;
+                if (t < T) {
+                    const float2 u = sample_control(c, vsh, kc, t);
+                    if (act) u_out[(size_t)t * c.K + k] = u;
+                    acc += smooth_cost(c, s);
+                    px[i] = s.x;
+                    py[i] = s.y;
+                    n = i + 1;
+                    if (c.use_ctrl) {
+                        const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
+                        ctrl = __fmaf_rn(c.gamma, term, ctrl);
+                    }
+                    bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
+                } else {
+                    px[i] = px[i > 0 ? i - 1 : 0];
+                    py[i] = py[i > 0 ? i - 1 : 0];
+                }
             }
-            bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
+            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, n_grp, e0, px, py, n, n_cand);
         }
         float S = __fmaf_rn(c.c_obs, (float)cnt, acc);
         if (c.use_ctrl) S += ctrl;
@@ -169,19 +216,34 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f;
         int cnt = 0;
-        for (int t = 0; t < T; ++t) {
-            acc += smooth_cost(c, s);
-            if (n_grp > 0) cnt += obstacle_hits_culled(otab, n_grp, e0, s.x, s.y, n_cand);
-            if (t + 1 < T) {  // the last draw cannot reach the risk cost
-                const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-                const float4 w = disturbance<kNoise>(c, r);
-                const float2 cc = ck[t];
-                bicycle_step(s, cc.x, cc.y, c.dt);
-                s.x += w.x;
-                s.y += w.y;
-                s.psi += w.z;
-                s.v += w.w;
+        for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points
+            float px[kCullSteps], py[kCullSteps];
+            int n = 0;
+#pragma unroll
+            for (int i = 0; i < kCullSteps; ++i) {
+                const int t = t0 + i;
+                if (t < T) {
+                    acc += smooth_cost(c, s);
+                    px[i] = s.x;
+                    py[i] = s.y;
+                    n = i + 1;
+                    if (t + 1 < T) {  // the last draw cannot reach the risk cost
+                        const uint4 r =
+                            philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
+                        const float4 w = disturbance<kNoise>(c, r);
+                        const float2 cc = ck[t];
+                        bicycle_step(s, cc.x, cc.y, c.dt);
+                        s.x += w.x;
+                        s.y += w.y;
+                        s.psi += w.z;
+                        s.v += w.w;
+                    }
+                } else {
+                    px[i] = px[i > 0 ? i - 1 : 0];
+                    py[i] = py[i > 0 ? i - 1 : 0];
+                }
             }
+            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, n_grp, e0, px, py, n, n_cand);
         }
         if (active) {
             L = __fmaf_rn(c.c_obs, (float)cnt, acc);
@@ -192,12 +254,12 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         vals[tid] = L;
         tail[tid] = __builtin_nanf("");
     }
-    int rank = M;
-    const float cv = cvar_epilogue(vals, tail, means, spb, M, c.n_tail, c.scale_risk, c.B, &rank);
+    int pos = M, id = m;
+    const float cv = cvar_epilogue(vals, tail, means, spb, M, c.n_tail, c.scale_risk, c.B, &pos, &id);
     if (active && m == 0) cvar_out[k] = cv;
     if (c.grad && active) {  // tail membership for the gradient
-        ranks[(size_t)k * M + m] = rank;
-        if (rank < c.n_tail) tail_idx[(size_t)k * c.n_tail + rank] = m;
+        ranks[(size_t)k * M + id] = pos;
+        if (pos < c.n_tail) tail_idx[(size_t)k * c.n_tail + pos] = id;
     }
     if (work && (tid & 63) == 0)
         atomicAdd(&work[(item * 16 + (tid >> 6)) & (kWorkSlots - 1)], (unsigned long long)n_cand);

@@ -17,11 +17,21 @@ def test_executed_model_counts_waves_groups_and_candidates():
     # 256 samples of 64 draws: 4 samples per workgroup of 256 threads, 64 workgroups of 4 waves
     assert bench.disturbed_waves(p) == 256
     base = bench.executed_flops(p, 10, 0.0)
-    assert base == 80.0 * 256 * 64 * 10 + 17.0 * 64 * 1 * 10 * 256 + (60.0 + 7.0 * 16) * 256 * 10
+    boxes = -(-10 // bench.CULL_STEPS)
+    assert base == (80.0 * 256 * 64 * 10 + (4.0 * 10 + 17.0 * 1 * boxes) * 64 * 256
+                    + (60.0 + 7.0 * 16) * 256 * 10)
     assert bench.executed_flops(p, 10, 3.0) - base == 5.0 * 64 * 3.0
     # the batched path runs workgroups of 256 threads whatever M is
     q = dict(K=256, T=10, M=129)
     assert bench.disturbed_waves(q) == 256 * 3 and bench.disturbed_waves(q, block=256) == 256 * 4
+
+
+def test_cull_steps_match_the_kernel():
+    import os
+    import re
+    path = os.path.join(os.path.dirname(bench.__file__), "paper_2209_12842_amd", "csrc", "step_device.h")
+    m = re.search(r"constexpr int kCullSteps = (\d+);", open(path).read())
+    assert m and int(m.group(1)) == bench.CULL_STEPS
 
 
 def test_traffic_record_is_used_only_for_the_kernel_it_measured(monkeypatch):
