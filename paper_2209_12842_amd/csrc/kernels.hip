@@ -124,7 +124,7 @@ int update_parts(int T) { return T >= 256 ? 1 : 256 / T; }
 
 size_t update_lds_bytes(int T, int G) {
     const size_t slices = (size_t)update_parts(T) * 2 * T;
-    const size_t merge = (size_t)G + 2 * (size_t)T;
+    const size_t merge = 2 * (size_t)G + 2 * (size_t)T;
     return 4 * (256 + (slices > merge ? slices : merge));
 }
 

@@ -143,6 +143,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         // the last sample (the obstacle test works on whole waves) and write
         // nothing.  V is staged into LDS (the controls' region, unused here),
         // so that no step waits for a global load ----
+        __builtin_amdgcn_s_setprio(0);
         float* vsh = reinterpret_cast<float*>(ctl);  // 2T floats <= 2 spb T
         for (int i = tid; i < 2 * T; i += blockDim.x) vsh[i] = V[i];
         __syncthreads();  // otab and V staged
@@ -188,6 +189,11 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     }
 
     // ---- disturbed rollouts: one lane per (sample, draw) ----
+    // Where nominal and disturbed waves share a SIMD, the disturbed ones take
+    // the issue slots first: there are M of them per sample against one
+    // nominal lane per sample, the step ends with the slowest disturbed
+    // workgroup, and the nominal waves still finish within that time.
+    __builtin_amdgcn_s_setprio(2);
     const int wg = item - c.n_nom_wg;
     for (int idx = tid; idx < spb * T; idx += blockDim.x) {
         const int sl = idx / T;
@@ -310,7 +316,7 @@ __device__ __forceinline__ float seg_min_256(const float* v, float* red) {
 //     in debug mode, w_hat; in gradient mode J, every w_hat and the list of
 //     samples of non-zero weight instead, V unchanged.
 // LDS (dynamic, ush): w[256] | slice sums [parts][2T], then for the merge
-// v[256] | scale[G] | vp[2T] (update_lds_bytes).
+// v[256] | scale[G] | zb[G] | vp[2T] (update_lds_bytes).
 template <int kB>
 __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int parts, const float* __restrict__ S,
                                              const float* __restrict__ cvar, const float2* __restrict__ u,
@@ -323,6 +329,17 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     const int k0 = b * 256;
     const int n = min(256, K - k0);
     const int stride = 2 + 2 * T;
+    const int slice = (n + parts - 1) / parts;
+
+    // The first batch of this thread's first slice of controls does not
+    // depend on the weights: its loads are issued before them.
+    float2 pre[kB];
+    const bool has_pre = tid < T * parts && (tid / T) * slice + kB <= min(n, (tid / T + 1) * slice);
+    if (has_pre) {
+        const float2* ut = u + (size_t)(tid % T) * K + k0 + (tid / T) * slice;
+#pragma unroll
+        for (int i = 0; i < kB; ++i) pre[i] = ut[i];
+    }
 
     // 1. modified costs and chunk weights
     for (int i = tid; i < 256; i += nt) {
@@ -340,7 +357,6 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     const float Z_b = seg_sum_256(wsh, red);  // also publishes wsh
 
     // 2. weighted control sums over slices of the chunk
-    const int slice = (n + parts - 1) / parts;
     for (int idx = tid; idx < T * parts; idx += nt) {
         const int t = idx % T;
         const int pr = idx / T;
@@ -348,6 +364,14 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
         const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
         int k = ka;
+        if (idx == tid && has_pre) {  // the prefetched batch, summed in the same order
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                ax = __fmaf_rn(wsh[k + i], pre[i].x, ax);
+                ay = __fmaf_rn(wsh[k + i], pre[i].y, ay);
+            }
+            k += kB;
+        }
         for (; k + kB <= kb; k += kB) {  // kB loads in flight, then the sums in order
             float2 uu[kB];
 #pragma unroll
@@ -401,21 +425,36 @@ __device__ __forceinline__ void update_merge(const StepConst& c, int G, const fl
     const int stride = 2 + 2 * T;
     float* vsh = ush;  // 256 per-virtual-thread values
     float* scale = vsh + 256;
-    float* vp = scale + G;
+    float* zb = scale + G;
+    float* vp = zb + G;
 
-    // virtual thread i (of 256) takes chunks i, i + 256, ...
+    // The first batch of the weighted sums (thread j < 2T) does not depend
+    // on beta or Z: its loads are issued first.
+    float pre[kB];
+    const bool has_pre = tid < 2 * T && kB <= G;
+    if (has_pre) {
+#pragma unroll
+        for (int i = 0; i < kB; ++i) pre[i] = part[(size_t)i * stride + 2 + tid];
+    }
+    // virtual thread i (of 256) takes chunks i, i + 256, ...; beta_b and Z_b
+    // are read once and kept in LDS
     for (int i = tid; i < 256; i += nt) {
         float m = __builtin_inff();
-        for (int bb = i; bb < G; bb += 256) m = fminf(m, part[(size_t)bb * stride]);
+        for (int bb = i; bb < G; bb += 256) {
+            const float be = part[(size_t)bb * stride];
+            scale[bb] = be;
+            zb[bb] = part[(size_t)bb * stride + 1];
+            m = fminf(m, be);
+        }
         vsh[i] = m;
     }
-    const float beta = seg_min_256(vsh, red);
+    const float beta = seg_min_256(vsh, red);  // also publishes scale (beta_b) and zb
     for (int i = tid; i < 256; i += nt) {
         float z = 0.0f;
         for (int bb = i; bb < G; bb += 256) {
-            const float sc = expf(-(part[(size_t)bb * stride] - beta) / c.lambda);
+            const float sc = expf(-(scale[bb] - beta) / c.lambda);
             scale[bb] = sc;
-            z = __fmaf_rn(part[(size_t)bb * stride + 1], sc, z);
+            z = __fmaf_rn(zb[bb], sc, z);
         }
         vsh[i] = z;
     }
@@ -424,6 +463,11 @@ __device__ __forceinline__ void update_merge(const StepConst& c, int G, const fl
     for (int j = tid; j < 2 * T; j += nt) {
         float acc = 0.0f;
         int bb = 0;
+        if (j == tid && has_pre) {  // the prefetched batch, summed in the same order
+#pragma unroll
+            for (int i = 0; i < kB; ++i) acc = __fmaf_rn(pre[i], scale[i], acc);
+            bb = kB;
+        }
         for (; bb + kB <= G; bb += kB) {  // kB loads in flight, then the sums in order
             float pv[kB];
 #pragma unroll
