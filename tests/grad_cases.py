@@ -25,6 +25,9 @@ CASES = [
          step=1),
     dict(name="p0", kw=dict(K=512, M=32, lam=5.0), vseed=4, step=4, vscale=(0.5, 0.2)),
     dict(name="c2", kw=dict(K=512, T=50, M=16, lam=100.0, c_bdry=1.0), vseed=4, step=1),
+    # tails sorted across waves: M = 128 (one exchange stage through LDS), M = 256 with risk scaling (three)
+    dict(name="c1", kw=dict(K=256, T=20, M=128, lam=10.0), vseed=4, step=2),
+    dict(name="c1", kw=dict(K=256, T=16, M=256, lam=5.0, B=0.5), vseed=4, step=1),
     dict(name="c4", kw=dict(lam=50.0), vseed=4, step=1),
 ]
 
