@@ -160,7 +160,12 @@ def _torch():
 
 
 def _stream_ptr(device) -> int:
+    """The current torch stream of `device` as a raw hipStream_t."""
     torch = _torch()
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:  # no Stream object per call (about 2 us less per step)
+        idx = device.index if isinstance(device, torch.device) else torch.device(device).index
+        return raw(torch.cuda.current_device() if idx is None else idx)
     return torch.cuda.current_stream(device).cuda_stream
 
 
@@ -215,8 +220,7 @@ class Controller:
         x = self._x0
         x[0], x[1], x[2], x[3] = (float(v) for v in x0)
         u0p = self._u0 if want_u0 else None
-        check(self._step_fn(self._h, x, V.data_ptr(), int(step_idx) & 0xFFFFFFFF, u0p,
-                            torch.cuda.current_stream(V.device).cuda_stream))
+        check(self._step_fn(self._h, x, V.data_ptr(), int(step_idx) & 0xFFFFFFFF, u0p, _stream_ptr(V.device)))
         if want_u0:
             return np.array([self._u0[0], self._u0[1]], dtype=np.float32)
         return None
@@ -232,7 +236,7 @@ class Controller:
         J = torch.empty((), dtype=torch.float32, device=V.device)
         g = torch.empty_like(V)
         check(lib().mppi_grad(self._h, x, V.data_ptr(), int(step_idx) & 0xFFFFFFFF, g.data_ptr(), J.data_ptr(),
-                              torch.cuda.current_stream(V.device).cuda_stream))
+                              _stream_ptr(V.device)))
         return J, g
 
     def debug(self) -> dict:
@@ -366,7 +370,7 @@ class Batch:
         idx = np.broadcast_to(np.asarray(step_idx, dtype=np.uint32), (self.n,))
         ctypes.memmove(self._idx, np.ascontiguousarray(idx).ctypes.data, 4 * self.n)
         check(lib().mppi_batch_step(self._h, self._x0, self._idx, self._u0 if want_u0 else None,
-                                    torch.cuda.current_stream(self.device).cuda_stream))
+                                    _stream_ptr(self.device)))
         if want_u0:
             return np.frombuffer(self._u0, dtype=np.float32).reshape(self.n, 2).copy()
         return None

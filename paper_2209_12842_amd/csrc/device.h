@@ -413,15 +413,32 @@ __device__ __forceinline__ float tail_sum(const float* tail, int n_tail) {
 
 // Wave64 reductions with a fixed butterfly order (results are identical on
 // every run and in every lane).
+__device__ __forceinline__ float xor_f32_32(float v) { return __int_as_float(lane_xor<32>(__float_as_int(v))); }
+__device__ __forceinline__ float xor_f32_16(float v) { return __int_as_float(lane_xor<16>(__float_as_int(v))); }
+__device__ __forceinline__ float xor_f32_8(float v) { return __int_as_float(lane_xor<8>(__float_as_int(v))); }
+__device__ __forceinline__ float xor_f32_4(float v) { return __int_as_float(lane_xor<4>(__float_as_int(v))); }
+__device__ __forceinline__ float xor_f32_2(float v) { return __int_as_float(lane_xor<2>(__float_as_int(v))); }
+__device__ __forceinline__ float xor_f32_1(float v) { return __int_as_float(lane_xor<1>(__float_as_int(v))); }
+
+// Butterfly over distances 32, 16, ..., 1 (lane exchanges of lane_xor); every
+// lane of the wave must be active.
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += xor_f32_32(v);
+    v += xor_f32_16(v);
+    v += xor_f32_8(v);
+    v += xor_f32_4(v);
+    v += xor_f32_2(v);
+    v += xor_f32_1(v);
     return v;
 }
 
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    v = fminf(v, xor_f32_32(v));
+    v = fminf(v, xor_f32_16(v));
+    v = fminf(v, xor_f32_8(v));
+    v = fminf(v, xor_f32_4(v));
+    v = fminf(v, xor_f32_2(v));
+    v = fminf(v, xor_f32_1(v));
     return v;
 }
 
