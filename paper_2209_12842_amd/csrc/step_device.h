@@ -334,9 +334,9 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     // The first batch of this thread's first slice of controls does not
     // depend on the weights: its loads are issued before them.
     float2 pre[kB];
-    const bool has_pre = tid < T * parts && (tid / T) * slice + kB <= min(n, (tid / T + 1) * slice);
+    const bool has_pre = tid < T * parts && (tid % parts) * slice + kB <= min(n, (tid % parts + 1) * slice);
     if (has_pre) {
-        const float2* ut = u + (size_t)(tid % T) * K + k0 + (tid / T) * slice;
+        const float2* ut = u + (size_t)(tid / parts) * K + k0 + (tid % parts) * slice;
 #pragma unroll
         for (int i = 0; i < kB; ++i) pre[i] = ut[i];
     }
@@ -358,8 +358,8 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
 
     // 2. weighted control sums over slices of the chunk
     for (int idx = tid; idx < T * parts; idx += nt) {
-        const int t = idx % T;
-        const int pr = idx / T;
+        const int t = idx / parts;  // neighbouring lanes read the slices of one row
+        const int pr = idx % parts;
         const int ka = pr * slice, kb = min(n, ka + slice);
         const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
