@@ -15,6 +15,9 @@ loop.  Synthetic seeded inputs.  One JSON line on stdout:
                state) is given beside it.  When the whole grid is resident
                the step is one launch whose duration also covers the update
                (about 3 % of the FLOPs, not counted)
+  serving      the same loop (same number of steps) through a persistent
+               serving session (mppi_serve_*: one resident launch, one
+               request per step): rollout-steps/s, ms per step and latency
   cpu_baseline the FP64 oracle on a bounded sample of the same workload,
                timed on this host's cores
 
@@ -258,6 +261,31 @@ def main():
                      "broad_phase_candidates_per_launch": cand,
                      "brute_force_equivalent_tflops": brute_tf},
     }
+    # the same loop through a persistent serving session (mppi_serve_*):
+    # one resident launch for all the steps, the same computation per step
+    try:
+        ctl.serve_start(V, idle_ms=5000)
+    except R.MppiError as e:  # the step does not run as one launch
+        out["serving"] = {"available": False, "reason": str(e)}
+    else:
+        base = n_total
+        lat_s = np.empty(args.steps)
+        for j in range(args.warmup):
+            u0 = ctl.serve_step(x, base + j)
+            x = plant_step(x, u0, dt32, wb32, plant_w[j])
+        t0 = time.perf_counter()
+        for j in range(args.steps):
+            s0 = time.perf_counter()
+            u0 = ctl.serve_step(x, base + args.warmup + j)
+            x = plant_step(x, u0, dt32, wb32, plant_w[(args.warmup + j) % n_total])
+            lat_s[j] = time.perf_counter() - s0
+        el_s = time.perf_counter() - t0
+        ctl.serve_stop()
+        assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(np.asarray(x)))
+        out["serving"] = {"available": True, "value": steps_per_call * args.steps / el_s,
+                          "ms_per_step": el_s / args.steps * 1e3,
+                          "latency_ms": {"p50": float(np.percentile(lat_s, 50) * 1e3),
+                                         "p99": float(np.percentile(lat_s, 99) * 1e3)}}
     if args.calibrate_copy > 0:
         n = args.calibrate_copy << 20
         src = torch.ones(n // 4, dtype=torch.float32, device=dev)

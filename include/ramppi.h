@@ -178,9 +178,42 @@ mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
 mppi_status mppi_grad(mppi_handle *h, const float x0[4], const float *V_dev, uint32_t step_idx,
                       float *grad_dev, float *J_dev, void *stream);
 
+/* ---- Persistent serving of the receding-horizon loop ----
+ *
+ * The step of Algorithm 1 repeated at each control instant (Sec. IV: the
+ * controller replans from every measured state), without one kernel launch
+ * per step: mppi_serve_start launches one kernel that stays resident on
+ * `stream` and runs one step per request.  Each served step computes
+ * exactly what mppi_step computes from the same x0, step_idx and V (same
+ * kernels' device code; bit-identical V+ and first command) and leaves V+
+ * (shifted when MPPI_F_SHIFT) in V_dev, which the session keeps.
+ *
+ * mppi_serve_start(h, V_dev, idle_ms, stream)
+ *   Only for handles whose step runs as one launch (every workgroup
+ *   resident at once; MPPI_EUNSUPPORTED otherwise, or when the serving
+ *   kernel itself cannot be resident).  The kernel occupies the GPU until
+ *   mppi_serve_stop, or until no request arrives for idle_ms milliseconds
+ *   (1 <= idle_ms <= 60000), when it leaves by itself.  While a session
+ *   runs, other work that needs the GPU's compute units waits behind it,
+ *   and mppi_step / mppi_grad on the handle return MPPI_EINVAL.
+ * mppi_serve_step(h, x0, step_idx, u0_host)
+ *   Posts the measured state (host, 4 floats, finite) and the step's call
+ *   index, waits for the step and writes the first command v+_0 (before
+ *   the shift) to u0_host (host, 2 floats).  MPPI_EDEVICE when the session
+ *   has ended by its idle limit (the handle is then no longer serving).
+ * mppi_serve_stop(h)
+ *   Ends the session and waits for the kernel to leave; MPPI_OK when no
+ *   session runs.
+ * Requests travel through mapped pinned host memory owned by the handle;
+ * one thread at a time may drive a session. */
+mppi_status mppi_serve_start(mppi_handle *h, float *V_dev, uint32_t idle_ms, void *stream);
+mppi_status mppi_serve_step(mppi_handle *h, const float x0[4], uint32_t step_idx, float *u0_host);
+mppi_status mppi_serve_stop(mppi_handle *h);
+
 /* Destroys the host handle (NULL is accepted); the workspace stays the
- * caller's.  Waits for nothing: the caller must not free the workspace while
- * a step is still running on the device. */
+ * caller's.  Ends a serving session first.  Waits for nothing else: the
+ * caller must not free the workspace while a step is still running on the
+ * device. */
 mppi_status mppi_destroy(mppi_handle *h);
 
 /* Message of the last non-OK status returned on this thread ("" if none). */

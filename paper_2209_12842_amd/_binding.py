@@ -76,6 +76,12 @@ def lib():
         L.mppi_grad.restype = I32
         L.mppi_destroy.argtypes = [V]
         L.mppi_destroy.restype = ctypes.c_int
+        L.mppi_serve_start.argtypes = [V, V, U32, V]
+        L.mppi_serve_start.restype = I32
+        L.mppi_serve_step.argtypes = [V, P(F), U32, P(F)]
+        L.mppi_serve_step.restype = I32
+        L.mppi_serve_stop.argtypes = [V]
+        L.mppi_serve_stop.restype = I32
         L.mppi_last_error.argtypes = []
         L.mppi_last_error.restype = ctypes.c_char_p
         L.mppi_debug_view.argtypes = [V, P(DebugPtrs)]
@@ -202,6 +208,8 @@ class Controller:
         self.K, self.T, self.M = self.p.K, self.p.T, self.p.M
         self._x0 = (ctypes.c_float * 4)()
         self._step_fn = L.mppi_step
+        self._serve_fn = L.mppi_serve_step
+        self._serve_V = None
 
     def new_V(self, V0=None):
         """A T x 2 float32 mean sequence on the controller's device."""
@@ -272,6 +280,29 @@ class Controller:
         n = ctypes.c_uint64()
         check(lib().mppi_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(n)))
         return n.value
+
+    def serve_start(self, V, idle_ms: int = 2000) -> None:
+        """Starts a persistent serving launch (mppi_serve_start) that keeps V
+        (T x 2 float32 on the device) for the session and runs one step per
+        serve_step call, each bit-identical to step(..., want_u0=True)."""
+        torch = _torch()
+        if not (V.is_cuda and V.dtype == torch.float32 and V.is_contiguous() and V.numel() == 2 * self.T):
+            raise ValueError("V must be a contiguous float32 CUDA tensor with T x 2 elements")
+        check(lib().mppi_serve_start(self._h, V.data_ptr(), int(idle_ms), _stream_ptr(V.device)))
+        self._serve_V = V  # the session writes it
+
+    def serve_step(self, x0, step_idx: int):
+        """Posts the measured state and returns the first command (2 floats)."""
+        x = self._x0
+        x[0], x[1], x[2], x[3] = (float(v) for v in x0)
+        check(self._serve_fn(self._h, x, int(step_idx) & 0xFFFFFFFF, self._u0))
+        return np.array([self._u0[0], self._u0[1]], dtype=np.float32)
+
+    def serve_stop(self) -> None:
+        """Ends the serving session (nothing to do when none runs)."""
+        if self._h:
+            check(lib().mppi_serve_stop(self._h))
+        self._serve_V = None
 
     def close(self) -> None:
         if self._h:

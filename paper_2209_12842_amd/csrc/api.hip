@@ -50,6 +50,12 @@ size_t rollout_lds_bytes(int spb, const mppi_params* p) {
     return 4 * (size_t)ramppi::rollout_otab_offset(spb, p->T, p->M) + 16 * 64 * (size_t)ramppi::rollout_n_grp(p->n_obs);
 }
 
+// Mapped pinned bytes per handle: the first command (2 floats), its
+// completion word, one spare word, then the serving request.
+constexpr size_t kPinnedBytes = 16 + sizeof(ramppi::ServeReq);
+// Longest idle limit of a serving launch.
+constexpr uint32_t kMaxServeIdleMs = 60000;
+
 // Launch geometry derived from the sizes.
 struct Geometry {
     int spb, block, n_nom_wg, G;
@@ -81,7 +87,7 @@ void derived_counts(const mppi_params* p, int* n_tail, int* n_warm) {
 
 // Workspace layout (byte offsets), each buffer 256-byte aligned.
 struct Layout {
-    size_t obs, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work, chunk, fuse;
+    size_t obs, u, S, cvar, S_tilde, w_hat, L, part, u0, counter, work, chunk, fuse, serve;
     // gradient buffers (MPPI_F_GRAD)
     size_t ranks, tail_idx, act_list, n_act, J, states, rows, rpart, gcounter;
     int R, stride, n_lane_blocks;
@@ -105,6 +111,7 @@ Layout layout(const mppi_params* p) {
     l.work = o;    o += align_up(8 * (size_t)ramppi::kWorkSlots);
     l.chunk = o;   o += align_up(4 * (size_t)g.G);
     l.fuse = o;    o += align_up(sizeof(ramppi::FuseArgs));
+    l.serve = o;   o += align_up(sizeof(ramppi::ServeReq) + sizeof(unsigned));  // request copy, go word
     l.ranks = l.tail_idx = l.act_list = l.n_act = l.J = l.states = l.rows = l.rpart = l.gcounter = 0;
     l.R = l.stride = l.n_lane_blocks = 0;
     if (p->flags & MPPI_F_GRAD) {
@@ -227,6 +234,10 @@ struct mppi_handle {
     float* u0_pinned_dev;  // its device address
     uint32_t u0_seq;       // last completion value requested
     bool fuse;             // one launch per step (the whole grid is resident at once)
+    bool serving;          // a persistent serving launch is resident (mppi_serve_start)
+    uint32_t serve_seq;    // last request posted in the session
+    hipStream_t serve_stream;
+    ramppi::ServeReq* req;  // mapped pinned host memory after the command words
     bool timing;
     std::vector<hipEvent_t> ev;  // 3 per timed step: start, after rollout, end
     int n_timed;
@@ -368,9 +379,14 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     h->timing = false;
     h->n_timed = 0;
     h->u0_seq = 0;
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->u0_pinned), 4 * sizeof(float),
+    h->serving = false;
+    h->serve_seq = 0;
+    h->serve_stream = nullptr;
+    // command (2 floats), completion word, then the serving request
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->u0_pinned), kPinnedBytes,
                                  hipHostMallocMapped | hipHostMallocCoherent);
-    if (e == hipSuccess) std::memset(h->u0_pinned, 0, 4 * sizeof(float));
+    if (e == hipSuccess) std::memset(h->u0_pinned, 0, kPinnedBytes);
+    h->req = e == hipSuccess ? reinterpret_cast<ramppi::ServeReq*>(h->u0_pinned + 4) : nullptr;
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "hipHostMalloc");
@@ -428,6 +444,7 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
 
 mppi_status mppi_destroy(mppi_handle* h) {
     if (!h) return MPPI_OK;
+    if (h->serving) (void)mppi_serve_stop(h);
     for (hipEvent_t ev : h->ev) (void)hipEventDestroy(ev);
     if (h->u0_pinned) (void)hipHostFree(h->u0_pinned);
     delete h;
@@ -441,6 +458,7 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     if (!h) return fail(MPPI_EINVAL, "handle is NULL");
     if (!x0) return fail(MPPI_EINVAL, "x0 is NULL");
     if (!V_dev) return fail(MPPI_EINVAL, "V_dev is NULL");
+    if (h->serving) return fail(MPPI_EINVAL, "the handle is serving (mppi_serve_stop first)");
     for (int i = 0; i < 4; ++i)
         if (!finite(x0[i])) return fail(MPPI_EINVAL, "x0[%d] is not finite", i);
     const mppi_params& p = h->p;
@@ -499,11 +517,121 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     return MPPI_OK;
 }
 
+mppi_status mppi_serve_start(mppi_handle* h, float* V_dev, uint32_t idle_ms, void* stream) {
+    if (!h) return fail(MPPI_EINVAL, "handle is NULL");
+    if (!V_dev) return fail(MPPI_EINVAL, "V_dev is NULL");
+    if (h->serving) return fail(MPPI_EINVAL, "the handle is already serving");
+    if (idle_ms < 1 || idle_ms > kMaxServeIdleMs)
+        return fail(MPPI_EINVAL, "idle_ms = %u outside [1, %u]", idle_ms, kMaxServeIdleMs);
+    if (!h->fuse) return fail(MPPI_EUNSUPPORTED, "the step does not run as one launch, so it cannot be served");
+    const mppi_params& p = h->p;
+    const Geometry& g = h->g;
+    const size_t lds = std::max(g.lds_rollout, g.lds_update);
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = ramppi::serve_capacity((int)p.noise_kind, g.block, lds, &per_cu);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e != hipSuccess) return hip_fail(e, "serving occupancy");
+    const int64_t grid = g.n_nom_wg + ((int64_t)p.K + g.spb - 1) / g.spb;
+    if ((int64_t)per_cu * n_cu < grid)
+        return fail(MPPI_EUNSUPPORTED, "the serving grid (%lld workgroups) cannot be resident at once",
+                    (long long)grid);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    ramppi::StepConst c;
+    const float x0[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // the per-step fields come with each request
+    fill_static(&c, p, g, h->n_tail, h->n_warm);
+    fill_dynamic(&c, p, x0, 0);
+    ramppi::StepBuffers bufs = step_buffers(h, V_dev);
+    // workspace: request copy | go word
+    char* sv = h->ws + h->l.serve;
+    ramppi::ServeArgs sa;
+    sa.req_host = reinterpret_cast<const ramppi::ServeReq*>(h->u0_pinned_dev + 4);
+    sa.req_dev = reinterpret_cast<ramppi::ServeReq*>(sv);
+    sa.go = reinterpret_cast<unsigned*>(sv + sizeof(ramppi::ServeReq));
+    sa.idle_ticks = 100000ull * idle_ms;  // s_memrealtime runs at 100 MHz
+
+    // a new session: requests and completions count from 1 again
+    std::memset(h->req, 0, sizeof(ramppi::ServeReq));
+    __atomic_store_n(reinterpret_cast<uint32_t*>(h->u0_pinned + 2), 0u, __ATOMIC_RELEASE);
+    e = hipMemsetAsync(sa.go, 0, sizeof(unsigned), s);
+    if (e == hipSuccess)
+        e = ramppi::launch_serve(c, bufs, g.block, lds,
+                                 reinterpret_cast<const ramppi::FuseArgs*>(h->ws + h->l.fuse), sa, s);
+    if (e != hipSuccess) return hip_fail(e, "serving launch");
+    h->serving = true;
+    h->serve_seq = 0;
+    h->serve_stream = s;
+    return MPPI_OK;
+}
+
+namespace {
+
+// Posts the next request: the per-step fields first, its number last.
+void post_request(mppi_handle* h, const ramppi::StepConst* c, uint32_t stop) {
+    ramppi::ServeReq* r = h->req;
+    if (c) {
+        r->step_idx = c->step_idx;
+        r->fx = c->fx;
+        r->fy = c->fy;
+        r->tox = c->tox;
+        r->toy = c->toy;
+        r->theta0 = c->theta0;
+        r->psi0 = c->psi0;
+        r->v0 = c->v0;
+    }
+    r->stop = stop;
+    __atomic_store_n(&r->seq, ++h->serve_seq, __ATOMIC_RELEASE);
+}
+
+}  // namespace
+
+mppi_status mppi_serve_step(mppi_handle* h, const float x0[4], uint32_t step_idx, float* u0_host) {
+    if (!h) return fail(MPPI_EINVAL, "handle is NULL");
+    if (!x0 || !u0_host) return fail(MPPI_EINVAL, "x0 or u0_host is NULL");
+    if (!h->serving) return fail(MPPI_EINVAL, "the handle is not serving (mppi_serve_start first)");
+    for (int i = 0; i < 4; ++i)
+        if (!finite(x0[i])) return fail(MPPI_EINVAL, "x0[%d] is not finite", i);
+    ramppi::StepConst c;
+    fill_dynamic(&c, h->p, x0, step_idx);
+    post_request(h, &c, 0u);
+    const uint32_t* word = reinterpret_cast<const uint32_t*>(h->u0_pinned + 2);
+    for (uint64_t spin = 1;; ++spin) {
+        if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == h->serve_seq) break;
+        if ((spin & 1023) == 0) {
+            const hipError_t q = hipStreamQuery(h->serve_stream);
+            if (q == hipSuccess) {  // the serving launch has left (its idle limit passed)
+                if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == h->serve_seq) break;
+                h->serving = false;
+                h->u0_seq = std::max(h->u0_seq, h->serve_seq);
+                return fail(MPPI_EDEVICE, "the serving launch has stopped (no request within its idle limit)");
+            }
+            if (q != hipErrorNotReady) return hip_fail(q, "serving readback");
+        }
+        __builtin_ia32_pause();
+    }
+    u0_host[0] = h->u0_pinned[0];
+    u0_host[1] = h->u0_pinned[1];
+    return MPPI_OK;
+}
+
+mppi_status mppi_serve_stop(mppi_handle* h) {
+    if (!h) return fail(MPPI_EINVAL, "handle is NULL");
+    if (!h->serving) return MPPI_OK;
+    post_request(h, nullptr, 1u);
+    const hipError_t e = hipStreamSynchronize(h->serve_stream);
+    h->serving = false;
+    // launched steps after the session use completion values above every served one
+    h->u0_seq = std::max(h->u0_seq, h->serve_seq);
+    if (e != hipSuccess) return hip_fail(e, "serving stop");
+    return MPPI_OK;
+}
+
 mppi_status mppi_grad(mppi_handle* h, const float x0[4], const float* V_dev, uint32_t step_idx, float* grad_dev,
                       float* J_dev, void* stream) {
     if (!h) return fail(MPPI_EINVAL, "handle is NULL");
     if (!(h->p.flags & MPPI_F_GRAD)) return fail(MPPI_EINVAL, "the handle was created without MPPI_F_GRAD");
     if (!x0 || !V_dev || !grad_dev) return fail(MPPI_EINVAL, "x0, V_dev or grad_dev is NULL");
+    if (h->serving) return fail(MPPI_EINVAL, "the handle is serving (mppi_serve_stop first)");
     for (int i = 0; i < 4; ++i)
         if (!finite(x0[i])) return fail(MPPI_EINVAL, "x0[%d] is not finite", i);
     const mppi_params& p = h->p;

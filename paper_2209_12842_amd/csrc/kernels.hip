@@ -40,6 +40,52 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __r
     }
 }
 
+// Persistent serving: the one-launch step in a loop, one iteration per
+// request (steps 1, 2, ... of the session).  Thread 0 of workgroup 0 takes
+// the requests from host memory; the others wait on its device-memory word.
+// Every wait is bounded, so every wave leaves even if no request comes.
+template <int kNoise>
+__global__ void __launch_bounds__(1024) k_serve(StepConst c0, const float4* __restrict__ obs, float* V,
+                                                float2* __restrict__ u_out, float* __restrict__ S_out,
+                                                float* __restrict__ cvar_out, float* __restrict__ L_out,
+                                                const FuseArgs* __restrict__ fa, ServeArgs sa) {
+    extern __shared__ float2 smem[];
+    __shared__ float red[16];
+    __shared__ int flag_sh;
+    __shared__ int fin_sh[8];
+    __shared__ int leave_sh;
+    for (unsigned seq = 1;; ++seq) {
+        if (threadIdx.x == 0) leave_sh = blockIdx.x == 0 ? serve_wait_leader(sa, seq) : serve_wait_member(sa, seq);
+        __syncthreads();
+        if (leave_sh) break;
+        // Every word of the step constants passes through an empty asm per
+        // request: the compiler then derives what the step needs (the
+        // Philox round keys, ...) inside the loop instead of keeping it live
+        // across requests, which spilled it into VGPR lanes of the hot loop.
+        StepConst c = c0;
+        {
+            uint32_t* wc = reinterpret_cast<uint32_t*>(&c);
+#pragma unroll
+            for (int i = 0; i < (int)(sizeof(StepConst) / 4); ++i) asm volatile("" : "+s"(wc[i]));
+        }
+        const ServeReq* r = sa.req_dev;
+        c.fx = r->fx;
+        c.fy = r->fy;
+        c.tox = r->tox;
+        c.toy = r->toy;
+        c.theta0 = r->theta0;
+        c.psi0 = r->psi0;
+        c.v0 = r->v0;
+        c.step_idx = r->step_idx;
+        c.u0_seq = seq;
+        rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem);
+        const FuseArgs f = *fa;
+        fused_update(c, f, blockIdx.x, S_out, cvar_out, u_out, V, reinterpret_cast<float*>(smem), red, &flag_sh,
+                     fin_sh);
+        __syncthreads();  // LDS and leave_sh are reused by the next request
+    }
+}
+
 __global__ void __launch_bounds__(256) k_update(StepConst c, int G, int parts, const float* __restrict__ S,
                                                 const float* __restrict__ cvar, const float2* __restrict__ u,
                                                 float* __restrict__ S_tilde, float* part, unsigned* counter,
@@ -118,6 +164,27 @@ hipError_t fused_rollout_capacity(int noise_kind, int block, size_t lds, int* bl
     if (noise_kind == 2)
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<2, true>, block, lds);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<0, true>, block, lds);
+}
+
+hipError_t serve_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu) {
+    if (noise_kind == 1) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_serve<1>, block, lds);
+    if (noise_kind == 2) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_serve<2>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_serve<0>, block, lds);
+}
+
+hipError_t launch_serve(const StepConst& c, const StepBuffers& b, int block, size_t lds, const FuseArgs* fa,
+                        const ServeArgs& sa, hipStream_t stream) {
+    const dim3 grid(c.n_nom_wg + (c.K + c.spb - 1) / c.spb);
+    if (c.noise_kind == 1)
+        hipLaunchKernelGGL(k_serve<1>, grid, dim3(block), lds, stream, c, b.obs, b.Vout, b.u, b.S, b.cvar, b.L, fa,
+                           sa);
+    else if (c.noise_kind == 2)
+        hipLaunchKernelGGL(k_serve<2>, grid, dim3(block), lds, stream, c, b.obs, b.Vout, b.u, b.S, b.cvar, b.L, fa,
+                           sa);
+    else
+        hipLaunchKernelGGL(k_serve<0>, grid, dim3(block), lds, stream, c, b.obs, b.Vout, b.u, b.S, b.cvar, b.L, fa,
+                           sa);
+    return hipGetLastError();
 }
 
 int update_parts(int T) { return T >= 256 ? 1 : 256 / T; }

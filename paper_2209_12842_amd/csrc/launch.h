@@ -104,6 +104,10 @@ hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, s
                           hipStream_t stream, int* ranks, int* tail_idx);
 // Workgroups of the one-launch step (rollouts and update) resident per CU.
 hipError_t fused_rollout_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu);
+// Persistent serving (k_serve): resident workgroups per CU, and the launch.
+hipError_t serve_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu);
+hipError_t launch_serve(const StepConst& c, const StepBuffers& b, int block, size_t lds, const FuseArgs* fa,
+                        const ServeArgs& sa, hipStream_t stream);
 hipError_t launch_grad(const StepConst& c, const StepBuffers& b, const GradArgs& a, const GradOut& go, int block,
                        size_t lds_rollout, int G, size_t lds_update, int n_lane_blocks, hipStream_t stream);
 hipError_t launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n, hipStream_t stream);

@@ -576,6 +576,81 @@ struct FuseArgs {
     int G, parts;
 };
 
+// ---- persistent serving: one resident launch runs step after step ----
+
+// One served step's request: the per-step constants the host derives from
+// the measured state (the same arithmetic as for a launched step), written
+// into mapped host memory with seq last; the leader workgroup copies it to
+// device memory for the others.
+struct ServeReq {
+    uint32_t seq;   // request number, 1, 2, ... within a session
+    uint32_t stop;  // non-zero: leave the loop
+    uint32_t step_idx;
+    uint32_t pad0;
+    float fx, fy, tox, toy, theta0, psi0, v0, pad1;
+};
+static_assert(sizeof(ServeReq) == 48, "ServeReq is read as three 16-byte words");
+
+struct ServeArgs {
+    const ServeReq* req_host;  // mapped host memory (device address)
+    ServeReq* req_dev;         // device copy read by every workgroup
+    unsigned* go;              // request number being served, or kServeExit
+    uint64_t idle_ticks;       // longest wait for a request (s_memrealtime ticks, 100 MHz)
+};
+
+constexpr unsigned kServeExit = 0xFFFFFFFFu;
+
+// Workgroup 0's thread 0: waits for request seq in host memory, copies it to
+// device memory and publishes seq in `go`; on a stop request or after
+// idle_ticks without one it publishes kServeExit.  Returns whether to leave.
+__device__ __forceinline__ bool serve_wait_leader(const ServeArgs& sa, unsigned seq) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        // relaxed polls (no cache invalidation while other workgroups may
+        // still be finishing the last step), one acquire once it has come
+        if (__hip_atomic_load(&sa.req_host->seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == seq) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            const ServeReq* r = sa.req_host;
+            if (__hip_atomic_load(&r->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) break;
+            // three 16-byte reads across PCIe instead of one per field
+            // (after the acquire above, so they see the posted request)
+            ServeReq* d = sa.req_dev;
+            const uint4 a = *reinterpret_cast<const uint4*>(r);
+            const float4 b = *reinterpret_cast<const float4*>(&r->fx);
+            const float4 e = *reinterpret_cast<const float4*>(&r->theta0);
+            d->step_idx = a.z;
+            d->fx = b.x;
+            d->fy = b.y;
+            d->tox = b.z;
+            d->toy = b.w;
+            d->theta0 = e.x;
+            d->psi0 = e.y;
+            d->v0 = e.z;
+            __hip_atomic_store(sa.go, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if (__builtin_amdgcn_s_memrealtime() - t0 > sa.idle_ticks) break;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(sa.go, kServeExit, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+// Thread 0 of every other workgroup: waits until `go` names request seq
+// (serve) or kServeExit (leave); leaves too after twice the leader's limit.
+__device__ __forceinline__ bool serve_wait_member(const ServeArgs& sa, unsigned seq) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (;;) {
+        const unsigned g = __hip_atomic_load(sa.go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (g == seq) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return false;
+        }
+        if (g == kServeExit || __builtin_amdgcn_s_memrealtime() - t0 > 2 * sa.idle_ticks) return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // Workgroups of a rollout launch whose samples fall in chunk b: the nominal
 // workgroups (block samples each) and the disturbed ones (spb samples each).
 __device__ __forceinline__ unsigned chunk_contributors(const StepConst& c, int b, int block) {
