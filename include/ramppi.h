@@ -205,7 +205,10 @@ mppi_status mppi_grad(mppi_handle *h, const float x0[4], const float *V_dev, uin
  *   Ends the session and waits for the kernel to leave; MPPI_OK when no
  *   session runs.
  * Requests travel through mapped pinned host memory owned by the handle;
- * one thread at a time may drive a session. */
+ * one thread at a time may drive a session.  One session per GPU at a time:
+ * a second one cannot become resident until the first ends (its steps then
+ * wait, at most until the first session's idle limit).  A session is not
+ * meant for HIP graph capture. */
 mppi_status mppi_serve_start(mppi_handle *h, float *V_dev, uint32_t idle_ms, void *stream);
 mppi_status mppi_serve_step(mppi_handle *h, const float x0[4], uint32_t step_idx, float *u0_host);
 mppi_status mppi_serve_stop(mppi_handle *h);

@@ -153,6 +153,10 @@ def test_step_and_views_reject_null(L):
     d = DebugPtrs()
     assert L.mppi_debug_view(None, ctypes.byref(d)) == MPPI_EINVAL
     assert L.mppi_timing_enable(None, 1) == MPPI_EINVAL
+    u0 = (ctypes.c_float * 2)()
+    assert L.mppi_serve_start(None, ctypes.c_void_p(1 << 20), 100, None) == MPPI_EINVAL
+    assert L.mppi_serve_step(None, x0, 0, u0) == MPPI_EINVAL
+    assert L.mppi_serve_stop(None) == MPPI_EINVAL
 
 
 def test_stage_entries_validate_first(L):
