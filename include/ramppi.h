@@ -226,10 +226,12 @@ const char *mppi_last_error(void);
 mppi_status mppi_debug_view(const mppi_handle *h, mppi_debug_ptrs *out);
 
 /* Kernel timing with HIP events recorded on the step's stream around the
- * rollout kernel and around the update kernel.  enable != 0 starts
- * recording (and clears earlier records); mppi_timing_read waits for the
- * recorded steps, returns the summed milliseconds and the step count, and
- * clears the records.  At most 4096 steps are kept. */
+ * rollout kernel and around the update kernel.  enable = 1 starts recording
+ * (and clears earlier records), enable = 2 resumes recording and keeps
+ * them, enable = 0 pauses (records kept), so that a caller can time a
+ * sample of its steps; mppi_timing_read waits for the recorded steps,
+ * returns the summed milliseconds and the step count, and clears the
+ * records.  At most 4096 steps are kept. */
 mppi_status mppi_timing_enable(mppi_handle *h, int enable);
 mppi_status mppi_timing_read(mppi_handle *h, double *rollout_ms, double *update_ms, int32_t *n_steps);
 

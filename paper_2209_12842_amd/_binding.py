@@ -265,8 +265,9 @@ class Controller:
         return dict(u=view(d.u, (T, K, 2)), S=view(d.S, (K,)), L=view(d.L, (K, M)), cvar=view(d.cvar, (K,)),
                     S_tilde=view(d.S_tilde, (K,)), w_hat=view(d.w_hat, (K,)), u0=view(d.u0, (2,)))
 
-    def timing_enable(self, on: bool = True) -> None:
-        check(lib().mppi_timing_enable(self._h, 1 if on else 0))
+    def timing_enable(self, on: bool = True, resume: bool = False) -> None:
+        """Start (clearing earlier records), resume (keeping them) or pause kernel timing."""
+        check(lib().mppi_timing_enable(self._h, (2 if resume else 1) if on else 0))
 
     def timing_read(self) -> tuple[float, float, int]:
         """(summed rollout-kernel ms, summed update-kernels ms, steps) since enable/read."""

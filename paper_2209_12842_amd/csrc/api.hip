@@ -697,7 +697,7 @@ mppi_status mppi_timing_enable(mppi_handle* h, int enable) {
         }
     }
     h->timing = enable != 0;
-    h->n_timed = 0;
+    if (enable == 1) h->n_timed = 0;  // 2 resumes, 0 pauses: the records stay
     return MPPI_OK;
 }
 
