@@ -1,6 +1,9 @@
 // Kernels of the RA-MPPI control step for gfx950.
 //
-// One step is two launches on the caller's stream:
+// One step is one launch of k_rollout when every workgroup of the step can
+// be resident at once (the update then runs in the workgroups that finish
+// each chunk: fused_update), else two launches on the caller's stream; a
+// serving session (k_serve) runs the one-launch step once per request:
 //   k_rollout   nominal workgroups (one lane per sample k: sampled controls,
 //               nominal rollout, cost S; Eq. 1-3) and disturbed workgroups
 //               (one lane per pair (k, m): disturbed rollout and risk cost L,
