@@ -154,27 +154,38 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
+        // one nominal state step: the sampled control, running and control
+        // costs at x_t, then x_{t+1}
+        auto step = [&](int t, float& px, float& py) {
+            const float2 u = sample_control(c, vsh, kc, t);
+            if (act) u_out[(size_t)t * c.K + k] = u;
+            acc += smooth_cost(c, s);
+            px = s.x;
+            py = s.y;
+            if (c.use_ctrl) {
+                const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
+                ctrl = __fmaf_rn(c.gamma, term, ctrl);
+            }
+            bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
+        };
         for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points
             float px[kCullSteps], py[kCullSteps];
-            int n = 0;
+            int n = kCullSteps;
+            if (t0 + kCullSteps <= T) {  // a whole run of steps with no branch between them
 #pragma unroll
-            for (int i = 0; i < kCullSteps; ++i) {
-                const int t = t0 + i;
-                if (t < T) {
-                    const float2 u = sample_control(c, vsh, kc, t);
-                    if (act) u_out[(size_t)t * c.K + k] = u;
-                    acc += smooth_cost(c, s);
-                    px[i] = s.x;
-                    py[i] = s.y;
-                    n = i + 1;
-                    if (c.use_ctrl) {
-                        const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
-                        ctrl = __fmaf_rn(c.gamma, term, ctrl);
+                for (int i = 0; i < kCullSteps; ++i) step(t0 + i, px[i], py[i]);
+            } else {
+                n = 0;
+#pragma unroll
+                for (int i = 0; i < kCullSteps; ++i) {
+                    const int t = t0 + i;
+                    if (t < T) {
+                        step(t, px[i], py[i]);
+                        n = i + 1;
+                    } else {
+                        px[i] = px[i > 0 ? i - 1 : 0];
+                        py[i] = py[i > 0 ? i - 1 : 0];
                     }
-                    bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
-                } else {
-                    px[i] = px[i > 0 ? i - 1 : 0];
-                    py[i] = py[i > 0 ? i - 1 : 0];
                 }
             }
             if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, n_grp, e0, px, py, n, n_cand);
@@ -222,31 +233,44 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f;
         int cnt = 0;
+        // one disturbed state step: running cost at x_t, then (t < T - 1; the
+        // last draw cannot reach the risk cost) x_{t+1}
+        auto step = [&](int t, bool advance, float& px, float& py) {
+            acc += smooth_cost(c, s);
+            px = s.x;
+            py = s.y;
+            if (advance) {
+                const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
+                const float4 w = disturbance<kNoise>(c, r);
+                const float2 cc = ck[t];
+                bicycle_step(s, cc.x, cc.y, c.dt);
+                s.x += w.x;
+                s.y += w.y;
+                s.psi += w.z;
+                s.v += w.w;
+            }
+        };
         for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points
             float px[kCullSteps], py[kCullSteps];
-            int n = 0;
+            int n = kCullSteps;
+            if (t0 + kCullSteps < T) {
+                // a whole run of steps with no branch between them, so that
+                // the noise of later steps can be computed beside the
+                // dynamics of earlier ones
 #pragma unroll
-            for (int i = 0; i < kCullSteps; ++i) {
-                const int t = t0 + i;
-                if (t < T) {
-                    acc += smooth_cost(c, s);
-                    px[i] = s.x;
-                    py[i] = s.y;
-                    n = i + 1;
-                    if (t + 1 < T) {  // the last draw cannot reach the risk cost
-                        const uint4 r =
-                            philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-                        const float4 w = disturbance<kNoise>(c, r);
-                        const float2 cc = ck[t];
-                        bicycle_step(s, cc.x, cc.y, c.dt);
-                        s.x += w.x;
-                        s.y += w.y;
-                        s.psi += w.z;
-                        s.v += w.w;
+                for (int i = 0; i < kCullSteps; ++i) step(t0 + i, true, px[i], py[i]);
+            } else {
+                n = 0;
+#pragma unroll
+                for (int i = 0; i < kCullSteps; ++i) {
+                    const int t = t0 + i;
+                    if (t < T) {
+                        step(t, t + 1 < T, px[i], py[i]);
+                        n = i + 1;
+                    } else {
+                        px[i] = px[i > 0 ? i - 1 : 0];
+                        py[i] = py[i > 0 ? i - 1 : 0];
                     }
-                } else {
-                    px[i] = px[i > 0 ? i - 1 : 0];
-                    py[i] = py[i > 0 ? i - 1 : 0];
                 }
             }
             if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, n_grp, e0, px, py, n, n_cand);
