@@ -181,8 +181,11 @@ __device__ __forceinline__ float tan_steer(float d) {
     return __builtin_amdgcn_sinf(r) * __builtin_amdgcn_rcpf(__builtin_amdgcn_cosf(r));
 }
 
-// Track and speed terms of q: c_dev e^2 + c_v (v - v_ref)^2 [+ c_bdry mu_bdry].
-__device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s) {
+// Track and speed terms of q: c_dev e^2 + c_v (v - v_ref)^2 [+ c_bdry mu_bdry
+// when kBdry; the rollouts pick the instantiation once, so that a run of
+// steps holds no branch].
+template <bool kBdry>
+__device__ __forceinline__ float smooth_cost_k(const StepConst& c, const State& s) {
     const float X = s.x + c.tox;
     const float Y = s.y + c.toy;
     const float xa = X * c.inv_a;
@@ -193,13 +196,17 @@ __device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s)
     const float gn2 = fmaxf(__fmaf_rn(gx, gx, gy * gy), 1e-24f);
     const float dv = s.v - c.v_ref;
     float q = __fmaf_rn(c.c_v * dv, dv, c.c_dev * (G * G * __builtin_amdgcn_rcpf(gn2)));
-    if (c.use_bdry) {
+    if (kBdry) {
         const float e = G * rsqrtf(gn2);
         const float d = c.hw - fabsf(e);
         const float mu = fmaxf(0.0f, atanf(-100.0f * d) * 0.318309886183790671538f + 0.5f);
         q = __fmaf_rn(c.c_bdry, mu, q);
     }
     return q;
+}
+
+__device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s) {
+    return c.use_bdry ? smooth_cost_k<true>(c, s) : smooth_cost_k<false>(c, s);
 }
 
 // Obstacle test (Eq. 22) on the table of a step (obstacle_entry): the point
@@ -316,11 +323,12 @@ __device__ __forceinline__ float2 sample_control(const StepConst& c, const float
     const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1);
     float z0, z1;
     box_muller(uniform01(r.x), uniform01(r.y), z0, z1);
-    float b0 = 0.0f, b1 = 0.0f;
-    if (k < c.n_warm) {
-        b0 = V[2 * t];
-        b1 = V[2 * t + 1];
-    }
+    // every lane reads v_t (t < T, in bounds) and warm samples keep it: a
+    // select, not a branch
+    const bool warm = k < c.n_warm;
+    const float v0 = V[2 * t], v1 = V[2 * t + 1];
+    const float b0 = warm ? v0 : 0.0f;
+    const float b1 = warm ? v1 : 0.0f;
     float a = __fmaf_rn(c.se0, z0, b0);
     float d = __fmaf_rn(c.se1, z1, b1);
     a = fminf(fmaxf(a, c.u_lo0), c.u_hi0);

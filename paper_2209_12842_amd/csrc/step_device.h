@@ -47,6 +47,16 @@ __host__ __device__ __forceinline__ int rollout_otab_offset(int spb, int T, int 
 
 __host__ __device__ __forceinline__ int rollout_n_grp(int n_obs) { return (n_obs + 63) >> 6; }
 
+// Compile-time switches for the per-step lambdas of the rollouts.
+struct BoolTrue {
+    static constexpr bool value = true;
+};
+struct BoolFalse {
+    static constexpr bool value = false;
+};
+constexpr BoolTrue kTrue{};
+constexpr BoolFalse kFalse{};
+
 // Slots of the broad-phase candidate counters (wave w of item i adds to slot
 // (16 i + w) mod kWorkSlots, spreading the atomics).
 constexpr int kWorkSlots = 256;
@@ -155,32 +165,39 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
         // one nominal state step: the sampled control, running and control
-        // costs at x_t, then x_{t+1}
-        auto step = [&](int t, float& px, float& py) {
+        // costs at x_t (the control cost is summed in every case and used
+        // when asked, so that the step holds no branch), then x_{t+1}
+        auto step = [&](auto bdry, int t, float& px, float& py) {
             const float2 u = sample_control(c, vsh, kc, t);
             if (act) u_out[(size_t)t * c.K + k] = u;
-            acc += smooth_cost(c, s);
+            acc += smooth_cost_k<decltype(bdry)::value>(c, s);
             px = s.x;
             py = s.y;
-            if (c.use_ctrl) {
-                const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
-                ctrl = __fmaf_rn(c.gamma, term, ctrl);
-            }
+            const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
+            ctrl = __fmaf_rn(c.gamma, term, ctrl);
             bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
         };
         for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points
             float px[kCullSteps], py[kCullSteps];
             int n = kCullSteps;
             if (t0 + kCullSteps <= T) {  // a whole run of steps with no branch between them
+                if (c.use_bdry) {
 #pragma unroll
-                for (int i = 0; i < kCullSteps; ++i) step(t0 + i, px[i], py[i]);
+                    for (int i = 0; i < kCullSteps; ++i) step(kTrue, t0 + i, px[i], py[i]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kCullSteps; ++i) step(kFalse, t0 + i, px[i], py[i]);
+                }
             } else {
                 n = 0;
 #pragma unroll
                 for (int i = 0; i < kCullSteps; ++i) {
                     const int t = t0 + i;
                     if (t < T) {
-                        step(t, px[i], py[i]);
+                        if (c.use_bdry)
+                            step(kTrue, t, px[i], py[i]);
+                        else
+                            step(kFalse, t, px[i], py[i]);
                         n = i + 1;
                     } else {
                         px[i] = px[i > 0 ? i - 1 : 0];
@@ -235,8 +252,8 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         int cnt = 0;
         // one disturbed state step: running cost at x_t, then (t < T - 1; the
         // last draw cannot reach the risk cost) x_{t+1}
-        auto step = [&](int t, bool advance, float& px, float& py) {
-            acc += smooth_cost(c, s);
+        auto step = [&](auto bdry, int t, bool advance, float& px, float& py) {
+            acc += smooth_cost_k<decltype(bdry)::value>(c, s);
             px = s.x;
             py = s.y;
             if (advance) {
@@ -257,15 +274,23 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
                 // a whole run of steps with no branch between them, so that
                 // the noise of later steps can be computed beside the
                 // dynamics of earlier ones
+                if (c.use_bdry) {
 #pragma unroll
-                for (int i = 0; i < kCullSteps; ++i) step(t0 + i, true, px[i], py[i]);
+                    for (int i = 0; i < kCullSteps; ++i) step(kTrue, t0 + i, true, px[i], py[i]);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < kCullSteps; ++i) step(kFalse, t0 + i, true, px[i], py[i]);
+                }
             } else {
                 n = 0;
 #pragma unroll
                 for (int i = 0; i < kCullSteps; ++i) {
                     const int t = t0 + i;
                     if (t < T) {
-                        step(t, t + 1 < T, px[i], py[i]);
+                        if (c.use_bdry)
+                            step(kTrue, t, t + 1 < T, px[i], py[i]);
+                        else
+                            step(kFalse, t, t + 1 < T, px[i], py[i]);
                         n = i + 1;
                     } else {
                         px[i] = px[i > 0 ? i - 1 : 0];
