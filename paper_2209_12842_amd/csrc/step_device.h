@@ -219,8 +219,10 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     // ---- disturbed rollouts: one lane per (sample, draw) ----
     // Where nominal and disturbed waves share a SIMD, the disturbed ones take
     // the issue slots first: there are M of them per sample against one
-    // nominal lane per sample, the step ends with the slowest disturbed
-    // workgroup, and the nominal waves still finish within that time.
+    // nominal lane per sample.  On the receding-horizon workload (K = 2048,
+    // M = 64) this order gave the shortest one-launch step of the three
+    // (equal priorities and nominal first were 2.7 us slower), although its
+    // nominal waves then finish a few microseconds after the disturbed ones.
     __builtin_amdgcn_s_setprio(2);
     const int wg = item - c.n_nom_wg;
     for (int idx = tid; idx < spb * T; idx += blockDim.x) {
