@@ -15,7 +15,11 @@ loop.  Synthetic seeded inputs.  One JSON line on stdout:
                brute-force-equivalent rate (every obstacle tested at every
                state) is given beside it.  When the whole grid is resident
                the step is one launch whose duration also covers the update
-               (about 3 % of the FLOPs, not counted)
+               (about 3 % of the FLOPs, not counted); valu_issue gives the
+               VALU instructions per SIMD per clock (counted by rocprofv3,
+               profiles/k_rollout_valu_counters.md) over the same duration
+               against the wave64 issue ceiling of 0.25, which is what
+               bounds the kernel
   serving      the same loop (same number of steps) through a persistent
                serving session (mppi_serve_*: one resident launch, one
                request per step): rollout-steps/s, ms per step and latency
@@ -136,6 +140,42 @@ def measured_traffic(workload: str):
     if vals.get("kernel sources sha256") != kernel_sources_sha256():
         return None
     return float(vals["fetch bytes per launch"]) + float(vals["write bytes per launch"])
+
+
+# MI355X: 256 CUs x 4 SIMDs at a 2.4 GHz engine clock; a wave64 VALU
+# instruction occupies its SIMD for at least 4 clocks.
+N_SIMD = 1024
+CLOCK_HZ = 2.4e9
+VALU_ISSUE_CEILING = 0.25
+
+
+def measured_valu(workload: str):
+    """VALU instructions per rollout launch (SQ_INSTS_VALU, whole device) from
+    the committed counter summary (profiles/k_rollout_valu_counters.md), or
+    None when there is none for the workload or the kernel sources changed."""
+    path = os.path.join(ROOT, "profiles", "k_rollout_valu_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel sources sha256") != kernel_sources_sha256():
+        return None
+    v = vals.get("%s VALU instructions per launch" % workload)
+    return float(v) if v is not None else None
+
+
+def valu_issue(workload: str, seconds_per_launch: float):
+    """VALU instructions issued per SIMD per clock over the measured launch
+    duration, against the wave64 issue ceiling; None without a record."""
+    n = measured_valu(workload)
+    if n is None or not seconds_per_launch > 0:
+        return None
+    rate = n / (seconds_per_launch * CLOCK_HZ * N_SIMD)
+    return {"insts_per_launch": n, "per_simd_per_clock": rate, "ceiling": VALU_ISSUE_CEILING,
+            "frac": rate / VALU_ISSUE_CEILING}
 
 
 def plant_step(x, u, dt, wb, w):
@@ -271,7 +311,8 @@ def main():
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_rollout", "executed_flops_per_launch": flops,
                      "broad_phase_candidates_per_launch": cand,
-                     "brute_force_equivalent_tflops": brute_tf},
+                     "brute_force_equivalent_tflops": brute_tf,
+                     "valu_issue": valu_issue(args.workload, roll_avg_s)},
     }
     # the same loop through a persistent serving session (mppi_serve_*):
     # one resident launch for all the steps, the same computation per step

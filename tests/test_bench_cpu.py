@@ -41,3 +41,17 @@ def test_traffic_record_is_used_only_for_the_kernel_it_measured(monkeypatch):
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
     assert bench.measured_traffic("c2") is None and bench.measured_traffic("c3") is None
     assert bench.measured_traffic("c1") is None  # nothing measured
+
+
+def test_valu_record_is_used_only_for_the_kernel_it_measured(monkeypatch):
+    for wl in ("c2", "c3"):
+        n = bench.measured_valu(wl)
+        assert n is None or n > 0
+    assert bench.measured_valu("c1") is None  # nothing measured
+    r = bench.valu_issue("c3", 0.8e-3)
+    if r is not None:
+        assert abs(r["per_simd_per_clock"] - r["insts_per_launch"] / (0.8e-3 * 2.4e9 * 1024)) < 1e-12
+        assert r["frac"] == r["per_simd_per_clock"] / 0.25
+    assert bench.valu_issue("c3", 0.0) is None
+    monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
+    assert bench.measured_valu("c2") is None and bench.valu_issue("c3", 1e-3) is None
