@@ -465,13 +465,75 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     __syncthreads();  // LDS free for the caller
 }
 
+// The merge's last part, once vp (2T) holds V+ in LDS and beta, Z (and
+// invZ = 1 / Z) are known: V (shifted when asked), the first command and the
+// completion word, w_hat in debug mode; in gradient mode J, every w_hat and
+// the samples of non-zero weight instead, V unchanged.
+__device__ __forceinline__ void merge_finish(const StepConst& c, float beta, float Z, float invZ, const float* vp,
+                                             const float* __restrict__ S_tilde, float* __restrict__ V,
+                                             float* __restrict__ u0, float* __restrict__ u0_host,
+                                             float* __restrict__ w_hat, float* red, const GradOut* go) {
+    const int T = c.T, K = c.K;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __syncthreads();
+    if (go) {
+        // gradient mode: V stays as it is; write J = beta - lambda log(Z/K),
+        // every w_hat, and the samples of non-zero weight in increasing order
+        if (tid == 0) *go->J = beta - c.lambda * logf(Z / (float)K);
+        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+        int base = 0;
+        for (int k0b = 0; k0b < K; k0b += nt) {
+            const int k = k0b + tid;
+            float wk = 0.0f;
+            if (k < K) {
+                wk = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
+                w_hat[k] = wk;
+            }
+            const int flag = (k < K) && (wk > 0.0f);
+            // exclusive prefix of the flags in thread order (fixed, so the list is deterministic)
+            const uint64_t ball = __builtin_amdgcn_ballot_w64(flag);
+            const int in_wave = __builtin_popcountll(ball & ((1ull << lane) - 1ull));
+            __syncthreads();
+            if (lane == 0) red[wv] = __int_as_float(__builtin_popcountll(ball));
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int q = 0; q < nw; ++q) {
+                const int cq = __float_as_int(red[q]);
+                before += (q < wv) ? cq : 0;
+                total += cq;
+            }
+            if (flag) go->act_list[base + before + in_wave] = k;
+            base += total;
+        }
+        if (tid == 0) *go->n_act = base;
+        return;
+    }
+    const int shift = (c.flags & 2u) != 0;
+    for (int j = tid; j < 2 * T; j += nt) {
+        int src = j;
+        if (shift) src = min(j + 2, 2 * T - 2 + (j & 1));
+        V[j] = vp[src];
+    }
+    if (tid < 2) u0[tid] = vp[tid];
+    if (tid == 0 && u0_host) {  // mapped pinned host memory
+        u0_host[0] = vp[0];
+        u0_host[1] = vp[1];
+        if (c.u0_seq)  // completion word, ordered after the command at system scope
+            __hip_atomic_store(reinterpret_cast<unsigned*>(u0_host + 2), c.u0_seq, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (c.debug) {
+        for (int k = tid; k < K; k += nt) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
+    }
+}
+
 template <int kB>
 __device__ __forceinline__ void update_merge(const StepConst& c, int G, const float* __restrict__ part,
                                              const float* __restrict__ S_tilde, float* __restrict__ V,
                                              float* __restrict__ u0, float* __restrict__ u0_host,
                                              float* __restrict__ w_hat, float* ush, float* red,
                                              const GradOut* go = nullptr) {
-    const int T = c.T, K = c.K;
+    const int T = c.T;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int stride = 2 + 2 * T;
     float* vsh = ush;  // 256 per-virtual-thread values
@@ -539,56 +601,24 @@ __device__ __forceinline__ void update_merge(const StepConst& c, int G, const fl
         }
         vp[j] = acc * invZ;
     }
-    __syncthreads();
-    if (go) {
-        // gradient mode: V stays as it is; write J = beta - lambda log(Z/K),
-        // every w_hat, and the samples of non-zero weight in increasing order
-        if (tid == 0) *go->J = beta - c.lambda * logf(Z / (float)K);
-        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-        int base = 0;
-        for (int k0b = 0; k0b < K; k0b += nt) {
-            const int k = k0b + tid;
-            float wk = 0.0f;
-            if (k < K) {
-                wk = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
-                w_hat[k] = wk;
-            }
-            const int flag = (k < K) && (wk > 0.0f);
-            // exclusive prefix of the flags in thread order (fixed, so the list is deterministic)
-            const uint64_t ball = __builtin_amdgcn_ballot_w64(flag);
-            const int in_wave = __builtin_popcountll(ball & ((1ull << lane) - 1ull));
-            __syncthreads();
-            if (lane == 0) red[wv] = __int_as_float(__builtin_popcountll(ball));
-            __syncthreads();
-            int before = 0, total = 0;
-            for (int q = 0; q < nw; ++q) {
-                const int cq = __float_as_int(red[q]);
-                before += (q < wv) ? cq : 0;
-                total += cq;
-            }
-            if (flag) go->act_list[base + before + in_wave] = k;
-            base += total;
-        }
-        if (tid == 0) *go->n_act = base;
-        return;
-    }
-    const int shift = (c.flags & 2u) != 0;
-    for (int j = tid; j < 2 * T; j += nt) {
-        int src = j;
-        if (shift) src = min(j + 2, 2 * T - 2 + (j & 1));
-        V[j] = vp[src];
-    }
-    if (tid < 2) u0[tid] = vp[tid];
-    if (tid == 0 && u0_host) {  // mapped pinned host memory
-        u0_host[0] = vp[0];
-        u0_host[1] = vp[1];
-        if (c.u0_seq)  // completion word, ordered after the command at system scope
-            __hip_atomic_store(reinterpret_cast<unsigned*>(u0_host + 2), c.u0_seq, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
-    }
-    if (c.debug) {
-        for (int k = tid; k < K; k += nt) w_hat[k] = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
-    }
+    merge_finish(c, beta, Z, invZ, vp, S_tilde, V, u0, u0_host, w_hat, red, go);
+}
+
+// The merge when there is one chunk (K <= 256), run by the workgroup that
+// has just written its partial record: beta = beta_0, every scale is
+// exp(0) = 1 and Z = Z_0, so V+ = N_0 / Z_0 -- the bits of update_merge
+// with G = 1, without the counter, the reductions or a device-scope wait.
+__device__ __forceinline__ void update_merge_single(const StepConst& c, const float* part,
+                                                    const float* __restrict__ S_tilde, float* __restrict__ V,
+                                                    float* __restrict__ u0, float* __restrict__ u0_host,
+                                                    float* __restrict__ w_hat, float* ush, float* red,
+                                                    const GradOut* go = nullptr) {
+    const float beta = part[0];
+    const float Z = part[1];
+    const float invZ = 1.0f / Z;
+    float* vp = ush + 256 + 2;  // the place update_merge gives it for G = 1
+    for (int j = threadIdx.x; j < 2 * c.T; j += blockDim.x) vp[j] = part[2 + j] * invZ;
+    merge_finish(c, beta, Z, invZ, vp, S_tilde, V, u0, u0_host, w_hat, red, go);
 }
 
 // Thread 0 adds one to a device-scope counter with acquire-release order
@@ -745,7 +775,9 @@ __device__ __forceinline__ void fused_update(const StepConst& c, const FuseArgs&
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
     for (int i = 0; i < nf; ++i) {
         update_chunk<kFuseBatch>(c, fin_sh[i], f.parts, S, cvar, u, f.S_tilde, f.part, ush, red);
-        if (arrive_last(f.counter, (unsigned)f.G, flag_sh))
+        if (f.G == 1)  // its own record, visible to the workgroup after update_chunk's barrier
+            update_merge_single(c, f.part, f.S_tilde, V, f.u0, c.u0_seq ? f.u0_host : nullptr, f.w_hat, ush, red);
+        else if (arrive_last(f.counter, (unsigned)f.G, flag_sh))
             update_merge<kFuseBatch>(c, f.G, f.part, f.S_tilde, V, f.u0, c.u0_seq ? f.u0_host : nullptr, f.w_hat,
                                      ush, red);
     }
@@ -761,6 +793,10 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
                                             float* __restrict__ u0_host, float* __restrict__ w_hat, float* ush,
                                             float* red, int* flag_sh, const GradOut* go = nullptr) {
     update_chunk<16>(c, b, parts, S, cvar, u, S_tilde, part, ush, red);
+    if (G == 1) {
+        update_merge_single(c, part, S_tilde, V, u0, u0_host, w_hat, ush, red, go);
+        return;
+    }
     if (!arrive_last(counter, (unsigned)G, flag_sh)) return;
     update_merge<16>(c, G, part, S_tilde, V, u0, u0_host, w_hat, ush, red, go);
 }
