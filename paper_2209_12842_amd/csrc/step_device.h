@@ -480,32 +480,35 @@ __device__ __forceinline__ void merge_finish(const StepConst& c, float beta, flo
         // gradient mode: V stays as it is; write J = beta - lambda log(Z/K),
         // every w_hat, and the samples of non-zero weight in increasing order
         if (tid == 0) *go->J = beta - c.lambda * logf(Z / (float)K);
+        // thread i takes the contiguous samples [i q, (i + 1) q): its count of
+        // non-zero weights, an exclusive prefix of the counts in thread order
+        // (lane scan, then the wave totals), and its samples go to the list
+        // from there, so the list is in increasing order
         const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-        int base = 0;
-        for (int k0b = 0; k0b < K; k0b += nt) {
-            const int k = k0b + tid;
-            float wk = 0.0f;
-            if (k < K) {
-                wk = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
-                w_hat[k] = wk;
-            }
-            const int flag = (k < K) && (wk > 0.0f);
-            // exclusive prefix of the flags in thread order (fixed, so the list is deterministic)
-            const uint64_t ball = __builtin_amdgcn_ballot_w64(flag);
-            const int in_wave = __builtin_popcountll(ball & ((1ull << lane) - 1ull));
-            __syncthreads();
-            if (lane == 0) red[wv] = __int_as_float(__builtin_popcountll(ball));
-            __syncthreads();
-            int before = 0, total = 0;
-            for (int q = 0; q < nw; ++q) {
-                const int cq = __float_as_int(red[q]);
-                before += (q < wv) ? cq : 0;
-                total += cq;
-            }
-            if (flag) go->act_list[base + before + in_wave] = k;
-            base += total;
+        const int q = (K + nt - 1) / nt;
+        const int ka = min(K, tid * q), kb = min(K, ka + q);
+        int cnt = 0;
+        for (int k = ka; k < kb; ++k) {
+            const float wk = expf(-(S_tilde[k] - beta) / c.lambda) * invZ;
+            w_hat[k] = wk;
+            cnt += wk > 0.0f;
         }
-        if (tid == 0) *go->n_act = base;
+        int incl = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d);
+            if (lane >= d) incl += o;
+        }
+        if (lane == 63) red[wv] = __int_as_float(incl);
+        __syncthreads();
+        int pos = incl - cnt, total = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int cw = __float_as_int(red[w]);
+            pos += (w < wv) ? cw : 0;
+            total += cw;
+        }
+        for (int k = ka; k < kb; ++k)
+            if (w_hat[k] > 0.0f) go->act_list[pos++] = k;  // this thread's own stores
+        if (tid == 0) *go->n_act = total;
         return;
     }
     const int shift = (c.flags & 2u) != 0;
