@@ -19,14 +19,15 @@
 namespace ramppi {
 
 // du/dv of sample k at step t, per component (1 strictly inside the box for
-// warm samples, else 0), from the same control draw as sample_control.
-__device__ __forceinline__ float2 control_jacobian(const StepConst& c, const float* __restrict__ V, int k, int t) {
+// warm samples, else 0), from the same control draw as sample_control; v is
+// (v_t0, v_t1).
+__device__ __forceinline__ float2 control_jacobian(const StepConst& c, float2 v, int k, int t) {
     if (k >= c.n_warm) return make_float2(0.0f, 0.0f);
     const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1);
     float z0, z1;
     box_muller(uniform01(r.x), uniform01(r.y), z0, z1);
-    const float a = __fmaf_rn(c.se0, z0, V[2 * t]);
-    const float d = __fmaf_rn(c.se1, z1, V[2 * t + 1]);
+    const float a = __fmaf_rn(c.se0, z0, v.x);
+    const float d = __fmaf_rn(c.se1, z1, v.y);
     return make_float2((a > c.u_lo0 && a < c.u_hi0) ? 1.0f : 0.0f, (d > c.u_lo1 && d < c.u_hi1) ? 1.0f : 0.0f);
 }
 
@@ -59,11 +60,15 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
         for (int q = 0; q < 2 * T; ++q) a.rows[(size_t)q * a.stride + l] = 0.0f;
         return;
     }
-    // forward: the rollout again, keeping its states
+    // forward: the rollout again, keeping its states.  Each step's loads are
+    // issued one step ahead (a lane's chain of steps would otherwise wait a
+    // memory round trip per step).
     State s{0.0f, 0.0f, c.psi0, c.v0};
+    float2 u_next = a.u[k];
     for (int t = 0; t < T; ++t) {
         a.states[(size_t)t * a.stride + l] = make_float4(s.x, s.y, s.psi, s.v);
-        const float2 uu = a.u[(size_t)t * K + k];
+        const float2 uu = u_next;
+        if (t + 1 < T) u_next = a.u[(size_t)(t + 1) * K + k];
         bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
         if (m >= 0 && t + 1 < T) {
             const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
@@ -76,10 +81,19 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
     }
     // backward: lam = dCost/dx_{t}, seeded with the terminal cost (nominal only)
     float4 lam = (m < 0 && c.use_term) ? terminal_cost_grad(c, s) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float4 x_next = a.states[(size_t)(T - 1) * a.stride + l];
+    float2 uu_next = a.u[(size_t)(T - 1) * K + k];
+    float2 v_next = make_float2(a.V[2 * (T - 1)], a.V[2 * (T - 1) + 1]);
     for (int t = T - 1; t >= 0; --t) {
-        const float4 xv = a.states[(size_t)t * a.stride + l];
+        const float4 xv = x_next;
         const State x{xv.x, xv.y, xv.z, xv.w};
-        const float2 uu = a.u[(size_t)t * K + k];
+        const float2 uu = uu_next;
+        const float2 vt = v_next;
+        if (t > 0) {
+            x_next = a.states[(size_t)(t - 1) * a.stride + l];
+            uu_next = a.u[(size_t)(t - 1) * K + k];
+            v_next = make_float2(a.V[2 * (t - 1)], a.V[2 * (t - 1) + 1]);
+        }
         const float tn = tan_steer(uu.y);
         float r = x.psi * 0.159154943091895335769f;
         r = r - rintf(r);
@@ -95,11 +109,11 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
         nl.w = gq.w + __fmaf_rn(dt * cs, lam.x, __fmaf_rn(dt * sn, lam.y, __fmaf_rn(dt * tn * c.inv_wheelbase,
                                                                                    lam.z, lam.w)));
         lam = nl;
-        const float2 dudv = control_jacobian(c, a.V, k, t);
+        const float2 dudv = control_jacobian(c, vt, k, t);
         float g0 = gua * dudv.x, g1 = gud * dudv.y;
         if (m < 0 && c.use_ctrl) {  // d/dv of gamma v^T Sigma^-1 u(v)
-            g0 = __fmaf_rn(c.gamma * c.inv_var0, __fmaf_rn(a.V[2 * t], dudv.x, uu.x), g0);
-            g1 = __fmaf_rn(c.gamma * c.inv_var1, __fmaf_rn(a.V[2 * t + 1], dudv.y, uu.y), g1);
+            g0 = __fmaf_rn(c.gamma * c.inv_var0, __fmaf_rn(vt.x, dudv.x, uu.x), g0);
+            g1 = __fmaf_rn(c.gamma * c.inv_var1, __fmaf_rn(vt.y, dudv.y, uu.y), g1);
         }
         a.rows[(size_t)(2 * t) * a.stride + l] = coef * g0;
         a.rows[(size_t)(2 * t + 1) * a.stride + l] = coef * g1;
