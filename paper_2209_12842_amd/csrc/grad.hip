@@ -31,6 +31,9 @@ __device__ __forceinline__ float2 control_jacobian(const StepConst& c, float2 v,
     return make_float2((a > c.u_lo0 && a < c.u_hi0) ? 1.0f : 0.0f, (d > c.u_lo1 && d < c.u_hi1) ? 1.0f : 0.0f);
 }
 
+// Steps by which the gradient rollouts load ahead of their use.
+constexpr int kGradAhead = 4;
+
 template <int kNoise>
 __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) {
     const int l = blockIdx.x * 256 + threadIdx.x;
@@ -61,62 +64,87 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
         return;
     }
     // forward: the rollout again, keeping its states.  Each step's loads are
-    // issued one step ahead (a lane's chain of steps would otherwise wait a
-    // memory round trip per step).
+    // issued kGradAhead steps ahead (a lane's chain of steps would otherwise
+    // wait a memory round trip per step); the ring of loaded values is
+    // indexed by the unrolled position, so it stays in registers.
     State s{0.0f, 0.0f, c.psi0, c.v0};
-    float2 u_next = a.u[k];
-    for (int t = 0; t < T; ++t) {
-        a.states[(size_t)t * a.stride + l] = make_float4(s.x, s.y, s.psi, s.v);
-        const float2 uu = u_next;
-        if (t + 1 < T) u_next = a.u[(size_t)(t + 1) * K + k];
-        bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
-        if (m >= 0 && t + 1 < T) {
-            const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-            const float4 w = disturbance<kNoise>(c, r);
-            s.x += w.x;
-            s.y += w.y;
-            s.psi += w.z;
-            s.v += w.w;
+    float2 ur[kGradAhead];
+#pragma unroll
+    for (int i = 0; i < kGradAhead; ++i)
+        if (i < T) ur[i] = a.u[(size_t)i * K + k];
+    for (int tb = 0; tb < T; tb += kGradAhead) {
+#pragma unroll
+        for (int i = 0; i < kGradAhead; ++i) {
+            const int t = tb + i;
+            if (t < T) {
+                a.states[(size_t)t * a.stride + l] = make_float4(s.x, s.y, s.psi, s.v);
+                const float2 uu = ur[i];
+                if (t + kGradAhead < T) ur[i] = a.u[(size_t)(t + kGradAhead) * K + k];
+                bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
+                if (m >= 0 && t + 1 < T) {
+                    const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
+                    const float4 w = disturbance<kNoise>(c, r);
+                    s.x += w.x;
+                    s.y += w.y;
+                    s.psi += w.z;
+                    s.v += w.w;
+                }
+            }
         }
     }
-    // backward: lam = dCost/dx_{t}, seeded with the terminal cost (nominal only)
+    // backward: lam = dCost/dx_{t}, seeded with the terminal cost (nominal
+    // only); states, controls and v_t loaded kGradAhead steps ahead likewise
     float4 lam = (m < 0 && c.use_term) ? terminal_cost_grad(c, s) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float4 x_next = a.states[(size_t)(T - 1) * a.stride + l];
-    float2 uu_next = a.u[(size_t)(T - 1) * K + k];
-    float2 v_next = make_float2(a.V[2 * (T - 1)], a.V[2 * (T - 1) + 1]);
-    for (int t = T - 1; t >= 0; --t) {
-        const float4 xv = x_next;
-        const State x{xv.x, xv.y, xv.z, xv.w};
-        const float2 uu = uu_next;
-        const float2 vt = v_next;
-        if (t > 0) {
-            x_next = a.states[(size_t)(t - 1) * a.stride + l];
-            uu_next = a.u[(size_t)(t - 1) * K + k];
-            v_next = make_float2(a.V[2 * (t - 1)], a.V[2 * (t - 1) + 1]);
+    float4 xr[kGradAhead];
+    float2 uq[kGradAhead], vr[kGradAhead];
+#pragma unroll
+    for (int i = 0; i < kGradAhead; ++i) {
+        const int t = T - 1 - i;
+        if (t >= 0) {
+            xr[i] = a.states[(size_t)t * a.stride + l];
+            uq[i] = a.u[(size_t)t * K + k];
+            vr[i] = make_float2(a.V[2 * t], a.V[2 * t + 1]);
         }
-        const float tn = tan_steer(uu.y);
-        float r = x.psi * 0.159154943091895335769f;
-        r = r - rintf(r);
-        const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
-        const float dt = c.dt, dv = dt * x.v;
-        const float gua = dt * lam.w;                                                 // d v' / d a
-        const float gud = dv * __fmaf_rn(tn, tn, 1.0f) * c.inv_wheelbase * lam.z;     // d psi' / d delta
-        const float4 gq = smooth_cost_grad(c, x);
-        float4 nl;
-        nl.x = gq.x + lam.x;
-        nl.y = gq.y + lam.y;
-        nl.z = gq.z + __fmaf_rn(-dv * sn, lam.x, __fmaf_rn(dv * cs, lam.y, lam.z));
-        nl.w = gq.w + __fmaf_rn(dt * cs, lam.x, __fmaf_rn(dt * sn, lam.y, __fmaf_rn(dt * tn * c.inv_wheelbase,
-                                                                                   lam.z, lam.w)));
-        lam = nl;
-        const float2 dudv = control_jacobian(c, vt, k, t);
-        float g0 = gua * dudv.x, g1 = gud * dudv.y;
-        if (m < 0 && c.use_ctrl) {  // d/dv of gamma v^T Sigma^-1 u(v)
-            g0 = __fmaf_rn(c.gamma * c.inv_var0, __fmaf_rn(vt.x, dudv.x, uu.x), g0);
-            g1 = __fmaf_rn(c.gamma * c.inv_var1, __fmaf_rn(vt.y, dudv.y, uu.y), g1);
+    }
+    for (int tb = T - 1; tb >= 0; tb -= kGradAhead) {
+#pragma unroll
+        for (int i = 0; i < kGradAhead; ++i) {
+            const int t = tb - i;
+            if (t < 0) continue;
+            const float4 xv = xr[i];
+            const State x{xv.x, xv.y, xv.z, xv.w};
+            const float2 uu = uq[i];
+            const float2 vt = vr[i];
+            const int tn = t - kGradAhead;
+            if (tn >= 0) {
+                xr[i] = a.states[(size_t)tn * a.stride + l];
+                uq[i] = a.u[(size_t)tn * K + k];
+                vr[i] = make_float2(a.V[2 * tn], a.V[2 * tn + 1]);
+            }
+            const float tnd = tan_steer(uu.y);
+            float r = x.psi * 0.159154943091895335769f;
+            r = r - rintf(r);
+            const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+            const float dt = c.dt, dv = dt * x.v;
+            const float gua = dt * lam.w;                                                 // d v' / d a
+            const float gud = dv * __fmaf_rn(tnd, tnd, 1.0f) * c.inv_wheelbase * lam.z;   // d psi' / d delta
+            const float4 gq = smooth_cost_grad(c, x);
+            float4 nl;
+            nl.x = gq.x + lam.x;
+            nl.y = gq.y + lam.y;
+            nl.z = gq.z + __fmaf_rn(-dv * sn, lam.x, __fmaf_rn(dv * cs, lam.y, lam.z));
+            nl.w = gq.w + __fmaf_rn(dt * cs, lam.x, __fmaf_rn(dt * sn, lam.y, __fmaf_rn(dt * tnd * c.inv_wheelbase,
+                                                                                       lam.z, lam.w)));
+            lam = nl;
+            const float2 dudv = control_jacobian(c, vt, k, t);
+            float g0 = gua * dudv.x, g1 = gud * dudv.y;
+            if (m < 0 && c.use_ctrl) {  // d/dv of gamma v^T Sigma^-1 u(v)
+                g0 = __fmaf_rn(c.gamma * c.inv_var0, __fmaf_rn(vt.x, dudv.x, uu.x), g0);
+                g1 = __fmaf_rn(c.gamma * c.inv_var1, __fmaf_rn(vt.y, dudv.y, uu.y), g1);
+            }
+            a.rows[(size_t)(2 * t) * a.stride + l] = coef * g0;
+            a.rows[(size_t)(2 * t + 1) * a.stride + l] = coef * g1;
         }
-        a.rows[(size_t)(2 * t) * a.stride + l] = coef * g0;
-        a.rows[(size_t)(2 * t + 1) * a.stride + l] = coef * g1;
     }
 }
 
