@@ -150,14 +150,20 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
 
 // Sum of the gradient rows: block b adds rows [256 b, 256 b + 256), wave w
 // taking outputs q = w, w + 4, ... (lane i adds rows i, i + 64, i + 128,
-// i + 192, then the wave adds its lanes); the last block to finish adds the
-// block sums in block order, writes dJ/dV and resets its counter.
+// i + 192, then the wave adds its lanes).  Only the nb blocks that hold rows
+// work (the others would add zeros): with one, its sums are dJ/dV; else the
+// last of them to finish adds the block sums in block order, writes dJ/dV
+// and resets its counter.  Either way the bits are those of adding every
+// block's sum in order.
 __global__ void __launch_bounds__(256) k_grad_reduce(int T, int G3, GradArgs a) {
     __shared__ int is_last;
     const int n_rows = *a.n_act * a.R;
+    const int nb = max(1, min(G3, (n_rows + 255) / 256));
     const int b = blockIdx.x, tid = threadIdx.x;
+    if (b >= nb) return;  // uniform per block
     const int lane = tid & 63, wv = tid >> 6;
     const int l0 = b * 256;
+    float* out = nb == 1 ? a.grad_out : a.rpart + (size_t)b * 2 * T;
     for (int q = wv; q < 2 * T; q += 4) {
         const float* rq = a.rows + (size_t)q * a.stride + l0;
         float acc = 0.0f;
@@ -167,12 +173,13 @@ __global__ void __launch_bounds__(256) k_grad_reduce(int T, int G3, GradArgs a) 
             if (l0 + l < n_rows) acc += rq[l];
         }
         acc = wave_sum(acc);
-        if (lane == 0) a.rpart[(size_t)b * 2 * T + q] = acc;
+        if (lane == 0) out[q] = acc;
     }
+    if (nb == 1) return;
     __syncthreads();
     if (tid == 0) {
         const unsigned done = __hip_atomic_fetch_add(a.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (done == (unsigned)(G3 - 1));
+        is_last = (done == (unsigned)(nb - 1));
         if (is_last) __hip_atomic_store(a.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
@@ -181,14 +188,14 @@ __global__ void __launch_bounds__(256) k_grad_reduce(int T, int G3, GradArgs a) 
     for (int q = tid; q < 2 * T; q += 256) {
         float acc = 0.0f;
         int bb = 0;
-        for (; bb + 16 <= G3; bb += 16) {  // 16 loads in flight, then the sums in order
+        for (; bb + 16 <= nb; bb += 16) {  // 16 loads in flight, then the sums in order
             float pv[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) pv[i] = a.rpart[(size_t)(bb + i) * 2 * T + q];
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc += pv[i];
         }
-        for (; bb < G3; ++bb) acc += a.rpart[(size_t)bb * 2 * T + q];
+        for (; bb < nb; ++bb) acc += a.rpart[(size_t)bb * 2 * T + q];
         a.grad_out[q] = acc;
     }
 }
