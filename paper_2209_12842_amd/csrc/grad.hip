@@ -21,14 +21,16 @@ namespace ramppi {
 // du/dv of sample k at step t, per component (1 strictly inside the box for
 // warm samples, else 0), from the same control draw as sample_control; v is
 // (v_t0, v_t1).
+// Computed in every lane and selected (no branch).
 __device__ __forceinline__ float2 control_jacobian(const StepConst& c, float2 v, int k, int t) {
-    if (k >= c.n_warm) return make_float2(0.0f, 0.0f);
     const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1);
     float z0, z1;
     box_muller(uniform01(r.x), uniform01(r.y), z0, z1);
     const float a = __fmaf_rn(c.se0, z0, v.x);
     const float d = __fmaf_rn(c.se1, z1, v.y);
-    return make_float2((a > c.u_lo0 && a < c.u_hi0) ? 1.0f : 0.0f, (d > c.u_lo1 && d < c.u_hi1) ? 1.0f : 0.0f);
+    const bool warm = k < c.n_warm;
+    return make_float2((warm && a > c.u_lo0 && a < c.u_hi0) ? 1.0f : 0.0f,
+                       (warm && d > c.u_lo1 && d < c.u_hi1) ? 1.0f : 0.0f);
 }
 
 // Steps by which the gradient rollouts load ahead of their use.
@@ -65,31 +67,39 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
     }
     // forward: the rollout again, keeping its states.  Each step's loads are
     // issued kGradAhead steps ahead (a lane's chain of steps would otherwise
-    // wait a memory round trip per step); the ring of loaded values is
-    // indexed by the unrolled position, so it stays in registers.
+    // wait a memory round trip per step; the index is clamped, the extra
+    // loads at the end unused); the ring of loaded values is indexed by the
+    // unrolled position, so it stays in registers.  The disturbance is drawn
+    // in every lane and added where it belongs (a select, not a branch), so
+    // a whole run of kGradAhead steps is one block the compiler can
+    // interleave.
     State s{0.0f, 0.0f, c.psi0, c.v0};
+    const bool disturbed = m >= 0;
     float2 ur[kGradAhead];
 #pragma unroll
-    for (int i = 0; i < kGradAhead; ++i)
-        if (i < T) ur[i] = a.u[(size_t)i * K + k];
+    for (int i = 0; i < kGradAhead; ++i) ur[i] = a.u[(size_t)min(i, T - 1) * K + k];
+    auto fstep = [&](int t, float2& slot) {
+        a.states[(size_t)t * a.stride + l] = make_float4(s.x, s.y, s.psi, s.v);
+        const float2 uu = slot;
+        slot = a.u[(size_t)min(t + kGradAhead, T - 1) * K + k];
+        bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
+        const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
+        const float4 w = disturbance<kNoise>(c, r);
+        const bool add = disturbed && t + 1 < T;
+        const float nx = s.x + w.x, ny = s.y + w.y, np = s.psi + w.z, nv = s.v + w.w;
+        s.x = add ? nx : s.x;
+        s.y = add ? ny : s.y;
+        s.psi = add ? np : s.psi;
+        s.v = add ? nv : s.v;
+    };
     for (int tb = 0; tb < T; tb += kGradAhead) {
+        if (tb + kGradAhead <= T) {
 #pragma unroll
-        for (int i = 0; i < kGradAhead; ++i) {
-            const int t = tb + i;
-            if (t < T) {
-                a.states[(size_t)t * a.stride + l] = make_float4(s.x, s.y, s.psi, s.v);
-                const float2 uu = ur[i];
-                if (t + kGradAhead < T) ur[i] = a.u[(size_t)(t + kGradAhead) * K + k];
-                bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
-                if (m >= 0 && t + 1 < T) {
-                    const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-                    const float4 w = disturbance<kNoise>(c, r);
-                    s.x += w.x;
-                    s.y += w.y;
-                    s.psi += w.z;
-                    s.v += w.w;
-                }
-            }
+            for (int i = 0; i < kGradAhead; ++i) fstep(tb + i, ur[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kGradAhead; ++i)
+                if (tb + i < T) fstep(tb + i, ur[i]);
         }
     }
     // backward: lam = dCost/dx_{t}, seeded with the terminal cost (nominal
@@ -99,51 +109,53 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
     float2 uq[kGradAhead], vr[kGradAhead];
 #pragma unroll
     for (int i = 0; i < kGradAhead; ++i) {
-        const int t = T - 1 - i;
-        if (t >= 0) {
-            xr[i] = a.states[(size_t)t * a.stride + l];
-            uq[i] = a.u[(size_t)t * K + k];
-            vr[i] = make_float2(a.V[2 * t], a.V[2 * t + 1]);
-        }
+        const int t = max(T - 1 - i, 0);
+        xr[i] = a.states[(size_t)t * a.stride + l];
+        uq[i] = a.u[(size_t)t * K + k];
+        vr[i] = make_float2(a.V[2 * t], a.V[2 * t + 1]);
     }
+    const bool ctrl_term = m < 0 && c.use_ctrl;  // d/dv of gamma v^T Sigma^-1 u(v), nominal rollout only
+    auto bstep = [&](int t, float4& xs, float2& us, float2& vs) {
+        const float4 xv = xs;
+        const State x{xv.x, xv.y, xv.z, xv.w};
+        const float2 uu = us;
+        const float2 vt = vs;
+        const int tn = max(t - kGradAhead, 0);
+        xs = a.states[(size_t)tn * a.stride + l];
+        us = a.u[(size_t)tn * K + k];
+        vs = make_float2(a.V[2 * tn], a.V[2 * tn + 1]);
+        const float tnd = tan_steer(uu.y);
+        float r = x.psi * 0.159154943091895335769f;
+        r = r - rintf(r);
+        const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
+        const float dt = c.dt, dv = dt * x.v;
+        const float gua = dt * lam.w;                                                 // d v' / d a
+        const float gud = dv * __fmaf_rn(tnd, tnd, 1.0f) * c.inv_wheelbase * lam.z;   // d psi' / d delta
+        const float4 gq = smooth_cost_grad(c, x);
+        float4 nl;
+        nl.x = gq.x + lam.x;
+        nl.y = gq.y + lam.y;
+        nl.z = gq.z + __fmaf_rn(-dv * sn, lam.x, __fmaf_rn(dv * cs, lam.y, lam.z));
+        nl.w = gq.w + __fmaf_rn(dt * cs, lam.x, __fmaf_rn(dt * sn, lam.y, __fmaf_rn(dt * tnd * c.inv_wheelbase,
+                                                                                   lam.z, lam.w)));
+        lam = nl;
+        const float2 dudv = control_jacobian(c, vt, k, t);
+        float g0 = gua * dudv.x, g1 = gud * dudv.y;
+        const float h0 = __fmaf_rn(c.gamma * c.inv_var0, __fmaf_rn(vt.x, dudv.x, uu.x), g0);
+        const float h1 = __fmaf_rn(c.gamma * c.inv_var1, __fmaf_rn(vt.y, dudv.y, uu.y), g1);
+        g0 = ctrl_term ? h0 : g0;
+        g1 = ctrl_term ? h1 : g1;
+        a.rows[(size_t)(2 * t) * a.stride + l] = coef * g0;
+        a.rows[(size_t)(2 * t + 1) * a.stride + l] = coef * g1;
+    };
     for (int tb = T - 1; tb >= 0; tb -= kGradAhead) {
+        if (tb - (kGradAhead - 1) >= 0) {
 #pragma unroll
-        for (int i = 0; i < kGradAhead; ++i) {
-            const int t = tb - i;
-            if (t < 0) continue;
-            const float4 xv = xr[i];
-            const State x{xv.x, xv.y, xv.z, xv.w};
-            const float2 uu = uq[i];
-            const float2 vt = vr[i];
-            const int tn = t - kGradAhead;
-            if (tn >= 0) {
-                xr[i] = a.states[(size_t)tn * a.stride + l];
-                uq[i] = a.u[(size_t)tn * K + k];
-                vr[i] = make_float2(a.V[2 * tn], a.V[2 * tn + 1]);
-            }
-            const float tnd = tan_steer(uu.y);
-            float r = x.psi * 0.159154943091895335769f;
-            r = r - rintf(r);
-            const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
-            const float dt = c.dt, dv = dt * x.v;
-            const float gua = dt * lam.w;                                                 // d v' / d a
-            const float gud = dv * __fmaf_rn(tnd, tnd, 1.0f) * c.inv_wheelbase * lam.z;   // d psi' / d delta
-            const float4 gq = smooth_cost_grad(c, x);
-            float4 nl;
-            nl.x = gq.x + lam.x;
-            nl.y = gq.y + lam.y;
-            nl.z = gq.z + __fmaf_rn(-dv * sn, lam.x, __fmaf_rn(dv * cs, lam.y, lam.z));
-            nl.w = gq.w + __fmaf_rn(dt * cs, lam.x, __fmaf_rn(dt * sn, lam.y, __fmaf_rn(dt * tnd * c.inv_wheelbase,
-                                                                                       lam.z, lam.w)));
-            lam = nl;
-            const float2 dudv = control_jacobian(c, vt, k, t);
-            float g0 = gua * dudv.x, g1 = gud * dudv.y;
-            if (m < 0 && c.use_ctrl) {  // d/dv of gamma v^T Sigma^-1 u(v)
-                g0 = __fmaf_rn(c.gamma * c.inv_var0, __fmaf_rn(vt.x, dudv.x, uu.x), g0);
-                g1 = __fmaf_rn(c.gamma * c.inv_var1, __fmaf_rn(vt.y, dudv.y, uu.y), g1);
-            }
-            a.rows[(size_t)(2 * t) * a.stride + l] = coef * g0;
-            a.rows[(size_t)(2 * t + 1) * a.stride + l] = coef * g1;
+            for (int i = 0; i < kGradAhead; ++i) bstep(tb - i, xr[i], uq[i], vr[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kGradAhead; ++i)
+                if (tb - i >= 0) bstep(tb - i, xr[i], uq[i], vr[i]);
         }
     }
 }
