@@ -28,6 +28,9 @@ CASES = [
     # tails sorted across waves: M = 128 (one exchange stage through LDS), M = 256 with risk scaling (three)
     dict(name="c1", kw=dict(K=256, T=20, M=128, lam=10.0), vseed=4, step=2),
     dict(name="c1", kw=dict(K=256, T=16, M=256, lam=5.0, B=0.5), vseed=4, step=1),
+    # horizons shorter than the recomputed rollouts' four-step load ring
+    dict(name="c1", kw=dict(K=64, T=3, M=16, lam=30.0), vseed=4, step=1),
+    dict(name="c1", kw=dict(K=64, T=2, M=16, lam=30.0), vseed=4, step=1),
     dict(name="c4", kw=dict(lam=50.0), vseed=4, step=1),
 ]
 
