@@ -518,6 +518,11 @@ __device__ __forceinline__ void merge_finish(const StepConst& c, float beta, flo
         V[j] = vp[src];
     }
     if (tid < 2) u0[tid] = vp[tid];
+    // The completion word may release the next served step, whose workgroups
+    // read V: every wave's stores of V must precede thread 0's release, so
+    // the workgroup meets at a barrier first (with T > 32 the stores come
+    // from more than one wave).
+    if (u0_host) __syncthreads();
     if (tid == 0 && u0_host) {  // mapped pinned host memory
         u0_host[0] = vp[0];
         u0_host[1] = vp[1];

@@ -107,3 +107,55 @@ def test_zero_mean_samples_have_no_gradient_path():
     w = W.make_world("c1", K=8, M=5, T=6, eta=1.0, gamma=0.0)
     _, g = oracle.free_energy(w["params"], w["obstacles"], w["x0"], W.random_V(6, 6), 2, grad=True)
     assert np.all(g == 0.0)
+
+
+# ---- the value of J (its additive constant is not seen by the gradient) ----
+
+def _jworld(**kw):
+    w = W.make_world("c1", K=37, T=12, M=8, **kw)
+    return w["params"], w["obstacles"], w["x0"], W.random_V(12, 3, scale=(1.0, 0.2))
+
+
+def test_free_energy_of_equal_costs_is_that_cost():
+    # zero control noise and no warm-start split: every sample is the same
+    # sequence, and with A = 0 (no risk term, whose draws differ per sample)
+    # every S~_k is one value c; the soft minimum of K equal
+    # values is c itself for any K and lambda -- this fixes the 1/K inside
+    # the logarithm (without it J would be c - lambda log K)
+    for K in (1, 5, 37):
+        for lam in (0.5, 20.0):
+            p, obs, x0, V = _jworld(sigma_eps=(0.0, 0.0), gamma=0.0, lam=lam, A=0.0)
+            p = dict(p, K=K)
+            St = oracle.step(p, obs, x0, V, 2)["S_tilde"]
+            assert np.ptp(St) == 0.0
+            J = oracle.free_energy(p, obs, x0, V, 2)
+            assert abs(J - St[0]) <= 1e-12 * max(1.0, abs(St[0])), (K, lam, J, St[0])
+
+
+def test_free_energy_lies_between_the_minimum_and_the_mean():
+    # J = -lambda log mean_k exp(-S~_k / lambda): at least min S~ (every term
+    # is at most exp(-min/lambda)), at most min S~ + lambda log K (the minimum's
+    # own term is 1/K of the mean), and at most the mean of S~ (Jensen)
+    for lam in (0.3, 3.0, 30.0):
+        p, obs, x0, V = _jworld(gamma=0.0, lam=lam)
+        St = oracle.step(p, obs, x0, V, 1)["S_tilde"]
+        J = oracle.free_energy(p, obs, x0, V, 1)
+        K = len(St)
+        lam = float(np.float32(lam))  # the oracle takes every parameter rounded to float32
+        assert St.min() - 1e-9 <= J <= St.min() + lam * np.log(K) + 1e-9
+        assert J <= St.mean() + 1e-9
+
+
+def test_free_energy_limits_in_lambda():
+    # gamma = 0 keeps the sampled costs independent of lambda, so only the
+    # soft minimum changes: lambda -> 0 gives min S~ (within lambda log K),
+    # lambda -> infinity gives the plain mean (second order: the variance over
+    # 2 lambda)
+    p, obs, x0, V = _jworld(gamma=0.0, lam=1.0)
+    St = oracle.step(p, obs, x0, V, 4)["S_tilde"]
+    K = len(St)
+    J0 = oracle.free_energy(dict(p, lam=1e-6), obs, x0, V, 4)
+    assert abs(J0 - St.min()) <= 1.01e-6 * np.log(K) + 1e-9
+    lam = 1e7
+    Jinf = oracle.free_energy(dict(p, lam=lam), obs, x0, V, 4)
+    assert abs(Jinf - St.mean()) <= St.var() / lam + 1e-7 * max(1.0, abs(St.mean())), (Jinf, St.mean())

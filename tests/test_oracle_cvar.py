@@ -82,6 +82,40 @@ def test_ties_take_the_n_tail_largest():
     assert oracle.cvar(L, 0.7) == pytest.approx(3.5)
 
 
+def test_tied_var_is_where_the_reading_leaves_the_literal_rule():
+    # Eq. 12-13 read literally average every draw with L >= VaR (N_o of them);
+    # the reading averages the n_tail largest.  Brute force on rows drawn from
+    # a few values (many ties): the two agree exactly when N_o == n_tail (no
+    # draw below the k_alpha-th order statistic equals it), and otherwise the
+    # literal mean is the reading's n_tail values plus N_o - n_tail further
+    # copies of VaR, averaged over N_o.
+    rng = np.random.default_rng(5)
+    n_differ = 0
+    for trial in range(400):
+        M = int(rng.integers(2, 40))
+        alpha = float(rng.uniform(0.05, 0.95))
+        if abs(alpha * M - round(alpha * M)) < 1e-6:
+            continue
+        L = rng.integers(0, 4, size=M).astype(np.float64) * rng.uniform(0.5, 3.0)
+        lit, var, n_o = _brute_force_cvar(list(L), alpha)
+        ka, nt = oracle.tail_size(alpha, M)
+        got = oracle.cvar(L, alpha)
+        if n_o == nt:
+            assert got == pytest.approx(lit, rel=1e-12, abs=1e-12)
+        else:
+            n_differ += 1
+            assert n_o > nt
+            assert (got * nt + (n_o - nt) * var) / n_o == pytest.approx(lit, rel=1e-12, abs=1e-12)
+    assert n_differ > 50
+    # the structural case of impulse disturbances: draws with no jump follow
+    # one trajectory and tie; one jumped draw above 15 tied ones (M = 16,
+    # alpha = 0.9: k_alpha = 15, n_tail = 2)
+    L = np.array([4.0] * 15 + [10.0])
+    lit, var, n_o = _brute_force_cvar(list(L), 0.9)
+    assert (var, n_o) == (4.0, 16) and lit == pytest.approx((10.0 + 15 * 4.0) / 16)
+    assert oracle.cvar(L, 0.9) == pytest.approx((10.0 + 4.0) / 2)
+
+
 @pytest.mark.parametrize("alpha,const", [(0.7, 1.1589753807), (0.9, 1.7549833193), (0.95, 2.0627128075)])
 def test_gaussian_closed_form(alpha, const):
     # CVaR_alpha of N(mu, sigma^2) = mu + sigma phi(Phi^-1(alpha)) / (1 - alpha)

@@ -40,7 +40,10 @@ def _states(x0, n):
 
 @pytest.mark.parametrize("wl,n,kw", [("c1", 40, {}), ("c2", 25, {}),
                                      ("c1", 20, dict(K=300, M=300, noise_kind=1)),
-                                     ("c1", 20, dict(M=48, noise_kind=2, jump_prob=0.1, jump_size=0.45, B=2.0))])
+                                     ("c1", 20, dict(M=48, noise_kind=2, jump_prob=0.1, jump_size=0.45, B=2.0)),
+                                     # T = 45: the 90 values of V+ are stored by two waves of the merging
+                                     # workgroup, and 90 is not a multiple of 64
+                                     ("c2", 30, dict(K=1024, T=45, M=32))])
 def test_served_steps_equal_launched_steps(wl, n, kw):
     w = W.make_world(wl, **kw)
     p = dict(w["params"], shift=True)
