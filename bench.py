@@ -1,10 +1,11 @@
 """Benchmark of the RA-MPPI control step on one MI355X.
 
-Default workload (c2, the receding-horizon loop): K = 2048 samples, T = 50,
-M = 64 draws, 50 obstacles along a 100 m x 40 m oval, alpha = 0.9,
-lambda = 0.5, consecutive mppi_step calls with the shifted mean sequence,
-the first command read back every step and a host FP64 plant closing the
-loop.  Synthetic seeded inputs.  One JSON line on stdout:
+Default workload (c3, the large plain step): K = 16384 samples, T = 100,
+M = 128 draws (2.1e8 disturbed state steps per control step), 200 obstacles
+along a 100 m x 40 m oval, alpha = 0.9, lambda = 1, consecutive mppi_step
+calls with the shifted mean sequence, the first command read back every step
+and a host FP64 plant closing the loop.  Synthetic seeded inputs.  One JSON
+line on stdout:
 
   value        rollout-steps/s (K M T per step) over the timed steps
   roofline     the rollout kernel: the FP32 FLOPs of its rollouts per launch
@@ -23,10 +24,20 @@ loop.  Synthetic seeded inputs.  One JSON line on stdout:
   serving      the same loop (same number of steps) through a persistent
                serving session (mppi_serve_*: one resident launch, one
                request per step): rollout-steps/s, ms per step and latency
+  c2_receding_horizon  the latency configuration (K = 2048, T = 50, M = 64,
+               50 obstacles, 200 steps of the same loop): rate, latency
+               p50 / p99, kernel times, and the persistent serving loop
+  paper_shape  the paper's own sample counts (K = 1024, T = 30, M = 300,
+               10 obstacles on the 0.6 m paper-preset oval): update rate in Hz
+               beside the paper's
+  paper        the paper's update rate with its hardware (context only)
   cpu_baseline the FP64 oracle on a bounded sample of the same workload,
-               timed on this host's cores
+               timed on this host's cores (all of them, and one thread on a
+               subset of the samples), with the CPU model
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c3|c1|c4]
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|p0]
+
+With --workload other than c3 the line carries that workload only.
 
 Other legs (one JSON line each, not the default):
   --workload c5   batched serving: 64 independent controllers of uneven size
@@ -63,6 +74,15 @@ from paper_2209_12842_amd import workloads as W  # noqa: E402
 
 PEAK_FP32_TFLOPS = 157.3          # MI355X FP32 vector peak (256 CU x 256 FLOP/clk x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
+
+# The paper's update rate for its middle sample count (Sec. V-A, the
+# computation-time paragraph): 44.3 Hz with 1024 samples x 300 disturbance
+# draws (3.072e5 trajectories) over a 30-step horizon on an NVIDIA RTX 3090,
+# a tyre-model vehicle and unstated precision.  Context, not a target.
+PAPER_RATE = {"update_rate_hz": 44.3, "trajectories": 3.072e5, "K": 1024, "M": 300, "T": 30,
+              "rollout_steps_per_s": 44.3 * 3.072e5 * 30, "hardware": "NVIDIA GeForce RTX 3090",
+              "note": "the paper's vehicle has tyre dynamics and its precision is not stated; "
+                      "its rate covers its whole control loop"}
 
 
 def model_flops(p: dict, n_obs: int) -> float:
@@ -185,10 +205,24 @@ def plant_step(x, u, dt, wb, w):
             psi + dt * v * math.tan(float(u[1])) / wb + w[2], v + dt * float(u[0]) + w[3]]
 
 
-def cpu_baseline(world: dict, budget_s: float = 10.0) -> dict:
-    """The FP64 oracle as it stands, on every host core: complete control
-    steps of the same workload (same world, consecutive step indices) until
-    about `budget_s` seconds of work have run."""
+def cpu_model() -> str:
+    """The host CPU's model string (/proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(world: dict, budget_s: float = 10.0, single_k: int = 256) -> dict:
+    """The FP64 oracle as it stands, timed on this host: (a) on every host
+    core, complete control steps of the same workload (same world,
+    consecutive step indices) until about `budget_s` seconds have run (at
+    least one step); (b) on one thread, the first `single_k` samples of a step
+    (the same rollouts: every sample's draws depend only on its own index),
+    scaled to rollout-steps/s."""
     import oracle
     p = world["params"]
     cores = len(os.sched_getaffinity(0))
@@ -202,9 +236,23 @@ def cpu_baseline(world: dict, budget_s: float = 10.0) -> dict:
         if dt >= budget_s:
             break
     steps = n * p["K"] * p["M"] * p["T"]
-    return {"value": steps / dt, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d complete control steps of the workload (K=%d, M=%d, T=%d) in %.1f s, FP64, %d threads"
-                      % (n, p["K"], p["M"], p["T"], dt, cores)}
+    out = {"value": steps / dt, "unit": "rollout-steps/s", "cores": cores, "kind": "oracle",
+           "sample": "%d complete control steps of the workload (K=%d, M=%d, T=%d) in %.1f s, FP64, %d threads"
+                     % (n, p["K"], p["M"], p["T"], dt, cores),
+           "cpu_model": cpu_model()}
+    ks = min(single_k, int(p["K"]))
+    ps = dict(p, K=ks)
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.step(ps, world["obstacles"], world["x0"], world["V0"], 0,
+                diagnostics=False)
+    dt1 = time.perf_counter() - t0
+    out["single_thread"] = {"value": ks * p["M"] * p["T"] / dt1, "unit": "rollout-steps/s", "cores": 1,
+                            "sample": "the first %d of %d samples of one step (K=%d, M=%d, T=%d) in %.2f s, "
+                                      "FP64, 1 thread; a full step extrapolates to %.0f s"
+                                      % (ks, p["K"], ks, p["M"], p["T"], dt1, dt1 * p["K"] / ks)}
+    oracle.set_threads(cores)
+    return out
 
 
 def main():
@@ -212,7 +260,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default=None, choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default=None, choices=["c1", "c2", "c3", "c4", "c5", "p0"])
     ap.add_argument("--grad", action="store_true")
     ap.add_argument("--study", action="store_true")
     ap.add_argument("--seeds", type=int, default=8)
@@ -236,8 +284,42 @@ def main():
     if args.workload == "c5":
         return run_batch(args, R, torch)
     if args.workload is None:
-        args.workload = "c2"
-    world = W.make_world(args.workload)
+        args.workload = "c3"
+    out = run_plain(R, torch, args.workload, args.steps, args.warmup)
+    if args.workload == "c3":
+        # the latency configuration and the paper's own sample counts, as
+        # extra keys beside the headline (their own warm-up and step counts)
+        c2 = run_plain(R, torch, "c2", 200, 10)
+        out["c2_receding_horizon"] = {k: c2[k] for k in ("value", "ms_per_step", "latency_ms", "kernel_ms",
+                                                         "serving")}
+        out["c2_receding_horizon"]["config"] = c2["config"]["workload"]
+        out["c2_receding_horizon"]["roofline_frac"] = c2["roofline"]["frac"]
+        out["c2_receding_horizon"]["valu_issue"] = c2["roofline"]["valu_issue"]
+        ps = run_plain(R, torch, "p0", 200, 10, serving=False)
+        out["paper_shape"] = {
+            "config": ps["config"]["workload"], "value": ps["value"], "ms_per_step": ps["ms_per_step"],
+            "update_rate_hz": 1e3 / ps["ms_per_step"], "latency_ms": ps["latency_ms"],
+            "paper": PAPER_RATE}
+    out["paper"] = PAPER_RATE
+    if args.calibrate_copy > 0:
+        dev = torch.device("cuda", 0)
+        n = args.calibrate_copy << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = n
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W.make_world(args.workload))
+        out["gpu_over_cpu"] = out["value"] / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+def run_plain(R, torch, workload: str, steps: int, warmup: int, serving: bool = True) -> dict:
+    """Consecutive receding-horizon steps of one controller (shift, first
+    command read back, host FP64 plant): the bench line of the workload."""
+    world = W.make_world(workload)
     p = dict(world["params"])
     p["shift"] = True                      # receding horizon: V <- shifted V+
     obs = world["obstacles"]
@@ -249,7 +331,7 @@ def main():
     V = ctl.new_V(world["V0"])
     dt32, wb32 = float(np.float32(p["dt"])), float(np.float32(p["wheelbase"]))
     sw = np.sqrt(np.float32(p["sigma_w"]).astype(np.float64))
-    n_total = args.warmup + args.steps
+    n_total = warmup + steps
     plant_w = (np.random.default_rng(12345).standard_normal((n_total, 4)) * sw).tolist()
     x = [float(v) for v in world["x0"]]
 
@@ -259,20 +341,20 @@ def main():
         x = plant_step(x, u0, dt32, wb32, plant_w[j])
         return u0
 
-    for j in range(args.warmup):
+    for j in range(warmup):
         one_step(j)
     torch.cuda.synchronize()
     ctl.timing_enable(True)   # clear, then time every TIMING_EVERY-th step of the timed
     ctl.timing_enable(False)  # region (three events per timed step cost host time)
-    lat = np.empty(args.steps)
+    lat = np.empty(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for j in range(args.steps):
+    for j in range(steps):
         s0 = time.perf_counter()
         timed = j % TIMING_EVERY == 0
         if timed:
             ctl.timing_enable(True, resume=True)
-        one_step(args.warmup + j)
+        one_step(warmup + j)
         if timed:
             ctl.timing_enable(False)
         lat[j] = time.perf_counter() - s0
@@ -284,7 +366,7 @@ def main():
     assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(np.asarray(x)))
 
     steps_per_call = K * M * T
-    value = steps_per_call * args.steps / elapsed
+    value = steps_per_call * steps / elapsed
     roll_avg_s = roll_ms / max(n_timed, 1) * 1e-3
     flops = executed_flops(p, n_obs, cand)
     achieved_tf = flops / roll_avg_s / 1e12
@@ -294,64 +376,59 @@ def main():
         "value": value,
         "unit": "rollout-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded world: %d obstacles on an elliptic track, Philox noise)" % n_obs,
         "config": {"workload": "%s: K=%d T=%d M=%d n_obs=%d alpha=%g lambda=%g, shift + first-command readback"
-                               % (args.workload, K, T, M, n_obs, p["alpha"], p["lam"]),
+                               % (workload, K, T, M, n_obs, p["alpha"], p["lam"]),
                    "K": K, "T": T, "M": M, "n_obs": n_obs, "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "kernel_ms": {"rollout": roll_avg_s * 1e3, "update": upd_ms / max(n_timed, 1)},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(args.workload),
+                     "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(workload),
                      "kernel": "k_rollout", "executed_flops_per_launch": flops,
                      "broad_phase_candidates_per_launch": cand,
                      "brute_force_equivalent_tflops": brute_tf,
-                     "valu_issue": valu_issue(args.workload, roll_avg_s)},
+                     "valu_issue": valu_issue(workload, roll_avg_s)},
     }
     # the same loop through a persistent serving session (mppi_serve_*):
     # one resident launch for all the steps, the same computation per step
+    if not serving:
+        ctl.close()
+        return out
     try:
         ctl.serve_start(V, idle_ms=5000)
     except R.MppiError as e:  # the step does not run as one launch
         out["serving"] = {"available": False, "reason": str(e)}
+        out["kernel_ms"]["launches"] = "two: rollouts, then the update"
     else:
+        # "update" is then the gap between the events after the one launch
+        out["kernel_ms"]["launches"] = "one: the update runs in the rollout launch"
         base = n_total
-        lat_s = np.empty(args.steps)
-        for j in range(args.warmup):
+        lat_s = np.empty(steps)
+        for j in range(warmup):
             u0 = ctl.serve_step(x, base + j)
             x = plant_step(x, u0, dt32, wb32, plant_w[j])
         t0 = time.perf_counter()
-        for j in range(args.steps):
+        for j in range(steps):
             s0 = time.perf_counter()
-            u0 = ctl.serve_step(x, base + args.warmup + j)
-            x = plant_step(x, u0, dt32, wb32, plant_w[(args.warmup + j) % n_total])
+            u0 = ctl.serve_step(x, base + warmup + j)
+            x = plant_step(x, u0, dt32, wb32, plant_w[(warmup + j) % n_total])
             lat_s[j] = time.perf_counter() - s0
         el_s = time.perf_counter() - t0
         ctl.serve_stop()
         assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(np.asarray(x)))
-        out["serving"] = {"available": True, "value": steps_per_call * args.steps / el_s,
-                          "ms_per_step": el_s / args.steps * 1e3,
+        out["serving"] = {"available": True, "value": steps_per_call * steps / el_s,
+                          "ms_per_step": el_s / steps * 1e3,
                           "latency_ms": {"p50": float(np.percentile(lat_s, 50) * 1e3),
                                          "p99": float(np.percentile(lat_s, 99) * 1e3)}}
-    if args.calibrate_copy > 0:
-        n = args.calibrate_copy << 20
-        src = torch.ones(n // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = n
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(world)
-        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
-    print(json.dumps(out), flush=True)
     ctl.close()
+    return out
 
 
 def run_batch(args, R, torch):
@@ -567,10 +644,12 @@ def run_study(args, R, torch):
         w = np.random.default_rng(1000 + seed).standard_normal((n_steps, 4)) * sw
         x = [float(v) for v in world["x0"]]
         th_prev = math.atan2(x[1] / b, x[0] / a)
-        turned, coll, out, t0 = 0.0, 0, 0, time.perf_counter()
+        turned, coll, out, dist, t0 = 0.0, 0, 0, 0.0, time.perf_counter()
         for j in range(n_steps):
             u0 = ctl.step(x, V, (seed << 16) + j, want_u0=True)
+            xp = x
             x = plant_step(x, u0, dt32, wb32, w[j])
+            dist += math.hypot(x[0] - xp[0], x[1] - xp[1])
             d2 = (obs[:, 0] - x[0]) ** 2 + (obs[:, 1] - x[1]) ** 2
             coll += int(np.any(d2 < obs[:, 2] ** 2))
             G = (x[0] / a) ** 2 + (x[1] / b) ** 2 - 1.0
@@ -580,22 +659,35 @@ def run_study(args, R, torch):
             turned += (th - th_prev + math.pi) % (2 * math.pi) - math.pi
             th_prev = th
         ctl.close()
-        return dict(laps=turned / (2 * math.pi), collisions=coll, outside=out, s=time.perf_counter() - t0)
+        return dict(laps=turned / (2 * math.pi), collisions=coll, outside=out, dist=dist,
+                    s=time.perf_counter() - t0)
 
     res = {A: [run(A, s) for s in range(args.seeds)] for A in (0.0, 10.0)}
 
-    def stat(rs, key):
-        v = np.array([r[key] / max(r["laps"], 1e-9) for r in rs])
+    def per(rs, key, unit):
+        return np.array([r[key] / max(r[unit], 1e-9) for r in rs])
+
+    def mse(v):
         return float(v.mean()), float(v.std(ddof=1) / math.sqrt(len(v))) if len(v) > 1 else 0.0
 
     summary = {}
     for A, rs in res.items():
         name = "ra_mppi" if A > 0 else "mppi"
-        cm, cse = stat(rs, "collisions")
-        om, ose = stat(rs, "outside")
+        cm, cse = mse(per(rs, "collisions", "laps"))
+        om, ose = mse(per(rs, "outside", "laps"))
+        dm, dse = mse(per(rs, "collisions", "dist"))
         summary[name] = {"collision_steps_per_lap": cm, "collision_se": cse, "outside_steps_per_lap": om,
-                         "outside_se": ose, "laps_mean": float(np.mean([r["laps"] for r in rs])),
+                         "outside_se": ose, "collision_steps_per_m": dm, "collision_per_m_se": dse,
+                         "laps_mean": float(np.mean([r["laps"] for r in rs])),
+                         "metres_mean": float(np.mean([r["dist"] for r in rs])),
+                         "collision_steps_total": int(sum(r["collisions"] for r in rs)),
                          "ms_per_step": 1e3 * float(np.mean([r["s"] for r in rs])) / n_steps}
+    # paired by seed (both controllers see the same plant disturbances):
+    # MPPI minus RA-MPPI, per lap and per metre
+    for key, unit in (("per_lap", "laps"), ("per_m", "dist")):
+        d = per(res[0.0], "collisions", unit) - per(res[10.0], "collisions", unit)
+        m, se = mse(d)
+        summary["paired_difference_" + key] = {"mean": m, "se": se, "seeds": len(d)}
     out = {
         "metric": "collision steps per lap (plant inside an obstacle), closed loop on the p0 oval",
         "value": summary["ra_mppi"]["collision_steps_per_lap"], "unit": "steps/lap", "n_gpus": 1,

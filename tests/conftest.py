@@ -19,3 +19,12 @@ def _oracle_built():
     if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
         oracle.build(force=False)
     yield
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """With RAMPPI_PARITY_SUMMARY=<path>, write the report of every full-step
+    comparison with the oracle that ran in this session as a markdown table."""
+    path = os.environ.get("RAMPPI_PARITY_SUMMARY")
+    helpers = sys.modules.get("parity_helpers")
+    if path and helpers is not None and (helpers.REPORTS or helpers.GRAD_REPORTS):
+        helpers.write_reports(path)

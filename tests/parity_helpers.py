@@ -15,9 +15,22 @@ comparison therefore has three layers:
    the oracle by whole collision counts only (c_obs times an integer); rollouts
    that cross the ill-conditioned centre of the Sampson distance are held to
    1e-2 instead;
-3. end to end: V+ agrees to 1e-3 absolute when no excluded rollout belongs to a
-   sample of weight > 1e-6 and the weights are well conditioned (a first-order
-   bound of the V+ change from the measured cost differences is below 1e-3).
+3. end to end: V+ agrees to 1e-3 absolute.  The comparison is meaningful
+   when the weights are well conditioned: a first-order bound of the V+
+   change from the measured S~ differences of the samples of weight > 1e-6
+   (which a flipped collision count in such a sample would make large) is
+   below 1e-3; check_step asserts that this holds unless the caller declares
+   a workload built to cross obstacle edges (strict_e2e=False), where it is
+   logged instead.
+
+The excluded rollouts are counted in three classes, each with its own cap:
+near an obstacle edge (oracle margin < 1e-3 m; at most 1 % of K*M, or the
+caller's cap for collision-heavy worlds), through the ill-conditioned centre
+of the track (at most 1 %), and actual collision-count flips (at most a
+quarter of the near-edge ones, plus two).  The caps on the shares allow three
+binomial standard deviations on top, which matters only for the K nominal
+rollouts of the small workloads.  Every report is also kept in
+REPORTS so that a session can write them out.
 """
 from __future__ import annotations
 
@@ -34,6 +47,13 @@ MARGIN = 1e-3
 # checked loosely instead
 COND_MIN = 0.25
 LOOSE_RTOL = 1e-2
+MAX_NEAR_EDGE = 0.01
+MAX_ILL = 0.01
+
+# (tag, report) of every check_step call in this process, and of every
+# gradient comparison (tests/test_grad_gpu.py)
+REPORTS: list = []
+GRAD_REPORTS: list = []
 
 
 def rel_err(got, ref):
@@ -56,8 +76,20 @@ def gpu_step(ctl, x0, V0, step_idx):
     return out
 
 
-def check_step(p: dict, g: dict, o: dict, shift: bool = False, strict_e2e: bool = True) -> dict:
-    """Assert the three layers; return a report."""
+def _cap(frac: float, n: int) -> float:
+    """Largest count of n rollouts allowed in a class capped at the share
+    frac: frac n plus three binomial standard deviations (the counts of the
+    K nominal rollouts are small samples) plus two."""
+    return frac * n + 3.0 * np.sqrt(frac * n) + 2.0
+
+
+def check_step(p: dict, g: dict, o: dict, shift: bool = False, strict_e2e: bool = True,
+               max_near_edge: float = MAX_NEAR_EDGE, tag: str = "") -> dict:
+    """Assert the three layers; return a report (also appended to REPORTS).
+
+    max_near_edge: cap on the share of the K*M disturbed rollouts that pass
+    within 1e-3 m of an obstacle edge (a property of the workload that the
+    oracle reports, not of the device)."""
     K, T, M = int(p["K"]), int(p["T"]), int(p["M"])
     lam = float(np.float32(p["lam"]))
     alpha = float(np.float32(p["alpha"]))
@@ -108,10 +140,15 @@ def check_step(p: dict, g: dict, o: dict, shift: bool = False, strict_e2e: bool 
     eS = rel_err(g["S"], o["S"])
     rep["excluded_L"] = int((~okL).sum())
     rep["excluded_S"] = int((~okS).sum())
+    rep["near_edge_L"] = int((o["obs_margin"] < MARGIN).sum())
     rep["ill_conditioned_L"] = int((~condL).sum())
+    rep["ill_conditioned_S"] = int((~condS).sum())
     rep["L_max_rel"] = float(eL[okL].max()) if okL.any() else 0.0
     rep["S_max_rel"] = float(eS[okS].max()) if okS.any() else 0.0
-    assert rep["excluded_L"] <= max(2, 0.05 * K * M), rep
+    assert rep["near_edge_L"] <= _cap(max_near_edge, K * M), rep
+    assert rep["ill_conditioned_L"] <= _cap(MAX_ILL, K * M), rep
+    assert int((o["nom_margin"] < MARGIN).sum()) <= _cap(max_near_edge, K), rep
+    assert rep["ill_conditioned_S"] <= _cap(MAX_ILL, K), rep
     assert np.all(eL[okL] <= COST_RTOL), (rep, np.unravel_index(np.argmax(np.where(okL, eL, 0)), eL.shape))
     assert np.all(eS[okS] <= COST_RTOL), rep
     # an excluded rollout may differ only by whole collision counts: the
@@ -127,6 +164,9 @@ def check_step(p: dict, g: dict, o: dict, shift: bool = False, strict_e2e: bool 
             rep["flips_" + name] = int(np.count_nonzero(n))
             tol = np.where(cond[ex], COST_RTOL, LOOSE_RTOL)
             assert np.all(resid <= tol), (name, resid.max())
+            # a flip needs a rollout within the FP32 error band of an edge,
+            # far inside the 1e-3 m margin: few of the excluded ones flip
+            assert rep["flips_" + name] <= 2 + 0.25 * int(ex.sum()), rep
     clean = okL.all(axis=1) & okS
     e = rel_err(g["cvar"], o["cvar"])[clean]
     rep["cvar_max_rel"] = float(e.max()) if e.size else 0.0
@@ -138,20 +178,53 @@ def check_step(p: dict, g: dict, o: dict, shift: bool = False, strict_e2e: bool 
     assert np.all(e <= COST_RTOL), rep
 
     # ---- end to end ----
+    # The first-order bound kappa of the V+ change from the measured S~
+    # differences of the weighted samples covers every cause of a difference
+    # (rounding, an excluded rollout, a flipped collision or C_u indicator):
+    # a flip in a weighted sample makes kappa large, and a strict check then
+    # fails.
     sig = o["w_hat"] > 1e-6
-    flipped = sig & ~(clean & cu_ok)
+    rep["weighted_with_excluded"] = int((sig & ~(clean & cu_ok)).sum())
     dS = np.abs(g["S_tilde"] - o["S_tilde"])
     spread = np.max(np.abs(o["u"] - o["V_plus"][None]).reshape(K, -1) * o["w_hat"][:, None], axis=1).sum()
     kappa = 2.0 * (dS[sig].max() if sig.any() else 0.0) / lam * spread
     rep["kappa"] = float(kappa)
-    rep["e2e_applies"] = bool((not flipped.any()) and kappa < V_ATOL)
+    rep["e2e_applies"] = bool(kappa < V_ATOL)
     ref_next = o["V_next"] if shift else o["V_plus"]
     eV = np.abs(g["V_next"] - ref_next).max()
     rep["V_e2e_max_abs"] = float(eV)
-    if rep["e2e_applies"] and strict_e2e:
+    rep["n_weighted"] = int(sig.sum())
+    if strict_e2e:
+        assert rep["e2e_applies"], ("end-to-end comparison not meaningful", rep)
+    if rep["e2e_applies"]:
         assert eV <= V_ATOL, rep
     # the box holds on the device too
     lo = np.float32(p["u_lo"]).astype(np.float64)
     hi = np.float32(p["u_hi"]).astype(np.float64)
     assert np.all(g["V_next"] >= lo - 1e-6) and np.all(g["V_next"] <= hi + 1e-6)
+    rep["K"], rep["T"], rep["M"] = K, T, M
+    REPORTS.append((tag or str(p.get("config_id", "")), dict(rep)))
     return rep
+
+
+def write_reports(path: str) -> None:
+    """Markdown table of every check_step report of this process."""
+    cols = ("K", "T", "M", "n_weighted", "weighted_with_excluded", "near_edge_L", "ill_conditioned_L", "excluded_S", "flips_L", "flips_S",
+            "L_max_rel", "S_max_rel", "cvar_max_rel", "S_tilde_max_rel", "w_hat_stage_max_abs", "V_stage_max_abs",
+            "kappa", "e2e_applies", "V_e2e_max_abs")
+
+    def fmt(v):
+        if isinstance(v, float):
+            return "%.2e" % v
+        return str(v)
+    lines = ["| case | " + " | ".join(cols) + " |", "|" + "---|" * (len(cols) + 1)]
+    for tag, rep in REPORTS:
+        lines.append("| %s | " % tag + " | ".join(fmt(rep.get(c, "")) for c in cols) + " |")
+    if GRAD_REPORTS:
+        gcols = ("n_weighted", "J_abs_err", "max_abs_g", "max_abs_dg", "rel_dg", "dS", "tolerance",
+                 "elementwise_rel")
+        lines += ["", "| gradient case | " + " | ".join(gcols) + " |", "|" + "---|" * (len(gcols) + 1)]
+        for tag, rep in GRAD_REPORTS:
+            lines.append("| %s | " % tag + " | ".join(fmt(rep.get(c, "")) for c in gcols) + " |")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")

@@ -133,7 +133,7 @@ def test_batch_controller_against_oracle():
         g["V_next"] = d["V"].astype(np.float64)
         g["u0_host"] = u0[i].astype(np.float64)
         o = oracle.step(w["params"], w["obstacles"], w["x0"], w["V0"], int(idx[i]))
-        rep = check_step(w["params"], g, o, shift=True)
+        rep = check_step(w["params"], g, o, shift=True, tag="mixed batch controller %d" % i)
         _log("controller %d: %s" % (i, rep))
 
 
@@ -149,4 +149,35 @@ def test_full_serving_batch_matches_sampled_single_steps():
         ref = _plain([ws[i]], [ws[i]["x0"]], [ws[i]["V0"]], [2])[0]
         _same(_batch_state(b, i), ref, i)
         assert np.array_equal(u0[i], ref["u0h"])
+    b.close()
+
+
+def test_c5_batch_controllers_against_oracle():
+    # the 64-controller serving batch at its own shapes: the controller with
+    # the most obstacle tests (K=7680, T=68, M=124, 150 obstacles), the one
+    # with the most state steps (K=8192, T=90, M=100), the one with 200
+    # obstacles and the one with the largest M among the large fields
+    # (M=126, 191 obstacles), each checked against a complete oracle step
+    ws = W.make_batch(64)
+    n = len(ws)
+    b = R.Batch([w["params"] for w in ws], [w["obstacles"] for w in ws], debug=True)
+    x0s = np.stack([w["x0"] for w in ws])
+    idx = np.arange(n, dtype=np.uint32) + 5
+    u0 = b.step(x0s, idx)
+    torch.cuda.synchronize()
+    oracle.set_threads(min(16, max(1, len(__import__("os").sched_getaffinity(0)))))
+    picks = {31: (7680, 68, 124, 150), 27: (8192, 90, 100, 63), 2: (256, 23, 26, 200), 13: (3840, 49, 126, 191)}
+    for i, shape in picks.items():
+        w = ws[i]
+        p = w["params"]
+        assert (p["K"], p["T"], p["M"], len(w["obstacles"])) == shape, (i, shape)
+        _log("c5 controller %d: K=%d T=%d M=%d n_obs=%d" % ((i,) + shape))
+        d = _batch_state(b, i)
+        g = {k: d[k].astype(np.float64) for k in ("S", "L", "cvar", "S_tilde", "w_hat", "u0")}
+        g["u"] = np.transpose(d["u"], (1, 0, 2)).astype(np.float64)
+        g["V_next"] = d["V"].astype(np.float64)
+        g["u0_host"] = u0[i].astype(np.float64)
+        o = oracle.step(p, w["obstacles"], w["x0"], w["V0"], int(idx[i]))
+        rep = check_step(p, g, o, shift=bool(p.get("shift")), tag="c5 controller %d" % i)
+        _log("  " + ", ".join("%s=%s" % kv for kv in rep.items()))
     b.close()

@@ -7,11 +7,16 @@ held fixed (Eq. 2 with the modified costs of Eq. 16 and the weights of
 Eq. 17).  Tolerances, from the FP32 arithmetic of the device:
   J       |dJ| <= 1e-4 max(|J|, 1): J is a soft minimum of the S~, each within
           the rollout bound 1e-4 relative;
-  dJ/dV   max |dg| <= (2e-3 + 4 dS) max |g|, where dS = max_k |dS~_k| / lambda
-          over the weighted samples is the measured FP32 error of the modified
-          costs in units of lambda: the weights move by up to 2 dS relative
-          (first order), and the per-sample adjoints carry FP32 rounding over
-          T steps (2e-3).
+  dJ/dV   max |dg| <= (2e-3 + 2 dS) max |g|, where dS is the spread
+          (max - min) of the signed FP32 errors of the modified costs S~_k
+          over the weighted samples, in units of lambda.  The weights depend
+          only on differences of the S~ (a common shift cancels in Eq. 17),
+          so each log-weight moves by at most dS (first order) and each
+          weight by at most about 2 dS of itself; the per-sample adjoints
+          carry FP32 rounding over T steps (2e-3).  The whole factor is capped
+          at 1e-2: a case whose measured dS would allow more fails.  When a
+          single sample carries the weight (dS = 0), the gradient is that
+          sample's adjoint and is also checked element by element.
 Every case sits away from the jumps of the gradient (grad_cases).
 """
 import sys
@@ -23,6 +28,7 @@ import oracle
 from paper_2209_12842_amd import workloads as W
 
 from grad_cases import CASES, IDS, conditioning, inputs, well_conditioned
+from parity_helpers import GRAD_REPORTS
 
 pytestmark = pytest.mark.gpu
 
@@ -60,19 +66,36 @@ def _device_grad(w, V, step):
     return out
 
 
-def _compare(p, dev, J_ref, g_ref, o):
+G_CAP = 1e-2
+W_SIG = 1e-7
+
+
+def _compare(p, dev, J_ref, g_ref, o, tag=""):
     lam = float(np.float32(p["lam"]))
-    wk = o["w_hat"] > 1e-7
-    dS = float(np.abs(dev["S_tilde"][wk] - o["S_tilde"][wk]).max()) / lam
+    wk = o["w_hat"] > W_SIG
+    d = dev["S_tilde"][wk] - o["S_tilde"][wk]
+    dS = float(d.max() - d.min()) / lam
     gmax = float(np.abs(g_ref).max())
     err_g = float(np.abs(dev["g"] - g_ref).max())
     err_J = abs(dev["J"] - J_ref)
-    _log("  J %.6f / %.6f (|d| %.2e)  max|g| %.4g  max|dg| %.3e (%.2e rel)  dS %.2e  weights %d" % (
-        dev["J"], J_ref, err_J, gmax, err_g, err_g / max(gmax, 1e-30), dS, int(wk.sum())))
+    factor = G_RTOL + 2.0 * dS
+    _log("  J %.6f / %.6f (|d| %.2e)  max|g| %.4g  max|dg| %.3e (%.2e rel)  dS %.2e  tolerance %.2e rel  weights %d" % (
+        dev["J"], J_ref, err_J, gmax, err_g, err_g / max(gmax, 1e-30), dS, factor, int(wk.sum())))
+    rep = dict(n_weighted=int(wk.sum()), J_abs_err=float(err_J), max_abs_g=gmax, max_abs_dg=err_g,
+               rel_dg=err_g / max(gmax, 1e-30), dS=dS, tolerance=factor)
+    GRAD_REPORTS.append((tag, rep))
+    assert factor <= G_CAP, ("cost errors too large for a meaningful gradient check", dS)
     assert err_J <= J_RTOL * max(abs(J_ref), 1.0), (dev["J"], J_ref)
-    assert err_g <= (G_RTOL + 4.0 * dS) * gmax, (err_g, gmax, dS)
+    assert err_g <= factor * gmax, (err_g, gmax, dS)
     # the normalised weights of the forward pass match the oracle's
-    assert np.abs(dev["w_hat"] - o["w_hat"]).max() <= 4.0 * dS + 1e-5
+    assert np.abs(dev["w_hat"] - o["w_hat"]).max() <= 2.0 * dS + 1e-5
+    if int(wk.sum()) == 1 and float(o["w_hat"][~wk].sum()) <= 1e-6:
+        # one sample's adjoint: each component to 2e-3 relative, above a
+        # floor of 1e-2 max|g| for components that nearly cancel
+        e = np.abs(dev["g"] - g_ref) / np.maximum(np.abs(g_ref), 1e-2 * gmax)
+        _log("  single weighted sample: max elementwise rel %.2e" % e.max())
+        rep["elementwise_rel"] = float(e.max())
+        assert e.max() <= G_RTOL, e.max()
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
@@ -86,7 +109,8 @@ def test_gradient_matches_oracle(case):
     J_ref, g_ref = oracle.free_energy(p, w["obstacles"], w["x0"], V.astype(np.float64), case["step"], grad=True)
     dev = _device_grad(w, V, case["step"])
     assert np.array_equal(dev["V_after"], V)  # mppi_grad leaves V as it is
-    _compare(p, dev, J_ref, g_ref, o)
+    _compare(p, dev, J_ref, g_ref, o, tag="%s %s step=%d" % (case["name"], ",".join(
+        "%s=%s" % kv for kv in sorted(case["kw"].items())), case["step"]))
 
 
 def test_gradient_at_full_differentiation_workload():
@@ -101,7 +125,7 @@ def test_gradient_at_full_differentiation_workload():
     assert well_conditioned(c), c
     J_ref, g_ref = oracle.free_energy(p, w["obstacles"], w["x0"], V.astype(np.float64), 1, grad=True)
     dev = _device_grad(w, V, 1)
-    _compare(p, dev, J_ref, g_ref, o)
+    _compare(p, dev, J_ref, g_ref, o, tag="c4 full size")
 
 
 def test_gradient_is_deterministic_and_autograd_agrees():

@@ -113,13 +113,22 @@ def _world(name, **kw):
     return w["params"], w["obstacles"], w["x0"], w["V0"]
 
 
-def _run(p, obs, x0, V0, step_idx, shift=False, strict=True, allow_zero=False, split=False):
-    _log("step %s K=%d T=%d M=%d n_obs=%d idx=%d split=%d" % (p.get("config_id"), p["K"], p["T"], p["M"], len(obs),
-                                                            step_idx, split))
+# worlds built so that many rollouts cross obstacle edges (the paper preset's
+# 0.6 m wide oval with its discs, the dense fields): up to 3 % of the disturbed
+# rollouts pass within 1e-3 m of an edge there, against at most about 0.5 %
+# on the other workloads
+COLLISION_HEAVY = 0.03
+
+
+def _run(p, obs, x0, V0, step_idx, shift=False, strict=True, allow_zero=False, split=False, tag="",
+         max_near_edge=None):
+    tag = tag or "%s K=%d T=%d M=%d n_obs=%d" % (p.get("config_id"), p["K"], p["T"], p["M"], len(obs))
+    _log("step %s idx=%d split=%d" % (tag, step_idx, split))
     ctl = R.Controller(p, obs, debug=True, allow_zero_noise=allow_zero, split_update=split)
     g = gpu_step(ctl, x0, V0, step_idx)
     o = oracle.step(p, obs, x0, V0, step_idx)
-    rep = check_step(p, g, o, shift=shift, strict_e2e=strict)
+    kw = {} if max_near_edge is None else dict(max_near_edge=max_near_edge)
+    rep = check_step(p, g, o, shift=shift, strict_e2e=strict, tag=tag + (" split" if split else ""), **kw)
     _log("  " + ", ".join("%s=%s" % kv for kv in rep.items()))
     ctl.close()
     return g, o, rep
@@ -127,56 +136,45 @@ def _run(p, obs, x0, V0, step_idx, shift=False, strict=True, allow_zero=False, s
 
 def test_step_c1():
     p, obs, x0, V0 = _world("c1")
-    _, _, rep = _run(p, obs, x0, V0, 0)
-    assert rep["e2e_applies"]
-    _run(p, obs, x0, W.random_V(p["T"], 5, scale=(2.0, 0.4)), 3)
+    _run(p, obs, x0, V0, 0, tag="c1")
+    _run(p, obs, x0, W.random_V(p["T"], 5, scale=(2.0, 0.4)), 3, tag="c1 random V")
 
 
 def test_step_c2():
     p, obs, x0, V0 = _world("c2")
-    _run(p, obs, x0, V0, 0, shift=True)
+    _run(p, obs, x0, V0, 0, shift=True, tag="c2 shift")
+
+
+def test_step_c2_many_weighted_samples():
+    # at lambda = 0.5 one sample carries nearly all the weight; a large
+    # temperature spreads it over hundreds of samples, so that V+ is a true
+    # weighted average (Eq. 4) at the full size
+    p, obs, x0, V0 = _world("c2", lam=400.0)
+    _, _, rep = _run(p, obs, x0, W.random_V(p["T"], 12, scale=(1.0, 0.2)), 5, shift=True, tag="c2 lambda=400")
+    assert rep["n_weighted"] >= 100, rep
 
 
 def test_step_paper_preset_m128_and_m300():
     p, obs, x0, V0 = _world("p0", M=128)
-    _run(p, obs, x0, W.random_V(p["T"], 6, scale=(1.0, 0.3)), 2)
+    _run(p, obs, x0, W.random_V(p["T"], 6, scale=(1.0, 0.3)), 2, tag="p0 M=128", max_near_edge=COLLISION_HEAVY)
     p, obs, x0, V0 = _world("p0")
-    _run(p, obs, x0, V0, 1)
+    _run(p, obs, x0, V0, 1, tag="p0 M=300", max_near_edge=COLLISION_HEAVY)
 
 
-def test_step_c3_sampled():
+def test_step_c3_full():
+    # the largest workload (K=16384, T=100, M=128, 200 obstacles, 2.1e8
+    # disturbed state steps): every sample's S, L, CVaR and S~ and the
+    # end-to-end V+ against a complete oracle step
     p, obs, x0, V0 = _world("c3")
-    _log("c3 full size, sampled")
-    ctl = R.Controller(p, obs, debug=True)
-    g = gpu_step(ctl, x0, V0, 0)
-    K, M = p["K"], p["M"]
-    alpha = float(np.float32(p["alpha"]))
-    lam = float(np.float32(p["lam"]))
-    # stage-wise on every sample
-    cv = oracle.cvar_batch(g["L"], alpha)
-    assert np.all(np.abs(g["cvar"] - cv) <= 20 * 4 * 2.0 ** -24 * np.maximum(np.abs(g["L"]).max(axis=1), 1))
-    _, wh = oracle.weights(g["S_tilde"], lam)
-    assert np.abs(g["w_hat"] - wh).max() <= 1e-5
-    assert np.abs(g["V_next"] - oracle.update(wh, g["u"])).max() <= 1e-5
-    # the oracle's own rollouts of a spread of samples, including the best
-    ks = sorted(set(list(np.linspace(0, K - 1, 12).astype(int)) + [int(np.argmin(g["S_tilde"]))]))
-    u_o = oracle.controls(dict(p, K=K), V0, 0)
-    assert np.abs(u_o - g["u"]).max() <= 1e-5
-    n_bad = 0
-    for k in ks:
-        S, L = oracle.rollout_subset(p, obs, x0, V0, 0, k, 1)
-        Sn, mg, cd = oracle.nominal_cost(p, obs, x0, V0, u_o[k])
-        assert Sn == S[0]
-        eS = rel_err(g["S"][k], S[0])
-        if mg >= 1e-3 and cd >= 0.25:
-            assert eS <= 1e-4, (k, eS)
-        diag = np.array([oracle.disturbed_cost(p, obs, x0, u_o[k], k, m, 0)[1:] for m in range(M)])
-        eL = rel_err(g["L"][k], L[0])
-        ok = (diag[:, 0] >= 1e-3) & (diag[:, 1] >= 0.25)
-        n_bad += int((~ok).sum())
-        assert np.all(eL[ok] <= 1e-4), (k, eL.max())
-    assert n_bad <= 0.01 * len(ks) * M
-    ctl.close()
+    _run(p, obs, x0, V0, 0, tag="c3")
+
+
+def test_step_c3_full_many_weighted_samples():
+    # the same world at a temperature (and control-cost weight gamma = lambda)
+    # at which hundreds of samples carry weight
+    p, obs, x0, V0 = _world("c3", lam=20000.0)
+    _, _, rep = _run(p, obs, x0, W.random_V(p["T"], 13, scale=(1.0, 0.2)), 1, tag="c3 lambda=20000")
+    assert rep["n_weighted"] >= 100, rep
 
 
 def test_closed_loop_c2_steps():
@@ -196,7 +194,7 @@ def test_closed_loop_c2_steps():
         g["V_next"] = V.detach().cpu().numpy().astype(np.float64)
         g["u0_host"] = u0.astype(np.float64)
         o = oracle.step(p, obs, x.astype(np.float32), Vin, j)
-        rep = check_step(p, g, o, shift=True)
+        rep = check_step(p, g, o, shift=True, tag="c2 K=512 closed loop %d" % j)
         _log("  loop %d: %s" % (j, rep))
         # host plant: the nominal model plus a Philox disturbance
         z = oracle.normals4(W.plant_noise_counter(j), p["seed"])
@@ -259,7 +257,7 @@ def test_edge_shapes(kw, split):
     if n_obs is not None:
         obs = obs[:n_obs]
     V0 = W.random_V(p["T"], 3, scale=(1.0, 0.2))
-    _run(p, obs, x0, V0, 1, split=split)
+    _run(p, obs, x0, V0, 1, split=split, tag="edge %s" % ",".join("%s=%s" % kv for kv in sorted(kw.items())))
 
 
 def _dense_obstacles(n, seed, x0, r=(0.1, 0.5)):
@@ -283,7 +281,8 @@ def test_dense_obstacle_fields(n_obs, M):
     p, _, x0, _ = _world("c1", K=256, M=M, T=30, lam=50.0)
     obs = _dense_obstacles(n_obs, 11 + n_obs, x0)
     V0 = W.random_V(p["T"], 7, scale=(1.0, 0.2))
-    g, o, rep = _run(p, obs, x0, V0, 2, strict=False)
+    g, o, rep = _run(p, obs, x0, V0, 2, strict=False, tag="dense n_obs=%d M=%d" % (n_obs, M),
+                     max_near_edge=COLLISION_HEAVY)
     hits = float((o["L"] >= float(np.float32(p["c_obs"]))).mean())
     _log("  fraction of disturbed rollouts with a collision: %.3f" % hits)
     assert hits > 0.02
@@ -316,7 +315,7 @@ def test_one_launch_step_equals_split_update(name, kw):
 
 def test_shift_and_first_command():
     p, obs, x0, V0 = _world("c1", shift=True)
-    g, o, rep = _run(p, obs, x0, V0, 0, shift=True)
+    g, o, rep = _run(p, obs, x0, V0, 0, shift=True, tag="c1 shift")
     assert np.abs(g["u0_host"] - o["u0"]).max() <= 1e-3
 
 
@@ -327,7 +326,8 @@ def test_shift_and_first_command():
 def test_step_disturbance_forms(name, kw):
     # the paper's uniform and impulse disturbances (robustness experiments)
     p, obs, x0, V0 = _world(name, **kw)
-    _run(p, obs, x0, W.random_V(p["T"], 8, scale=(1.0, 0.2)), 1, shift=bool(p.get("shift")))
+    _run(p, obs, x0, W.random_V(p["T"], 8, scale=(1.0, 0.2)), 1, shift=bool(p.get("shift")),
+         tag="%s noise_kind=%d" % (name, kw["noise_kind"]), max_near_edge=COLLISION_HEAVY if name == "p0" else None)
 
 
 def test_disturbance_forms_stage_parity():
