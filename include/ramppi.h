@@ -154,6 +154,33 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
 
+/* mppi_step for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * RA-MPPI iteration without a handle or a workspace.  The step's workspace is
+ * a static device array of the library (32 MiB per device, held from the
+ * first call on a device until the process ends; its address is looked up
+ * once per device); the call allocates nothing, neither device nor host
+ * memory.
+ *   p             parameters as for mppi_create; MPPI_F_DEBUG and MPPI_F_GRAD
+ *                 are rejected (MPPI_EINVAL: they need a handle),
+ *                 MPPI_F_SPLIT_UPDATE is implied, MPPI_F_SHIFT is honoured.
+ *                 MPPI_EUNSUPPORTED when the step's workspace
+ *                 (mppi_workspace_bytes) exceeds 32 MiB.
+ *   obstacles_dev device, n_obs x 3 floats (cx, cy, r), r > 0 (not checked:
+ *                 the values stay on the device); may be NULL when n_obs = 0.
+ *   x0, step_idx  as for mppi_step.
+ *   V_dev         device, T x 2 floats: in V, out V+ (as for mppi_step).
+ *   u0_dev        device, 2 floats receiving the first command before any
+ *                 shift, or NULL.
+ * Enqueues three kernels on `stream` (obstacle staging and counter reset,
+ * rollouts, update) and returns; the results equal those of mppi_step with
+ * the same inputs, bit for bit.  Every call on a device shares that device's
+ * scratch, which keeps the last call's contents: calls that overlap on one
+ * device (on different streams, or from several threads) race and must be
+ * ordered by the caller. */
+mppi_status mppi_step_noalloc(const mppi_params *p, const float *obstacles_dev, const float x0[4], float *V_dev,
+                              uint32_t step_idx, float *u0_dev, void *stream);
+
 /* Free energy of the sampled costs and its gradient with respect to V, for
  * differentiating through one controller step (Eq. 2, with the modified
  * costs of Eq. 14-16 and the weights of Eq. 17; noise held fixed):

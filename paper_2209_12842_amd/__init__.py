@@ -9,8 +9,8 @@ kernels for gfx950 behind a C ABI (include/ramppi.h), with this thin binding.
 """
 from ._binding import (MPPI_F_ALLOW_ZERO_NOISE, MPPI_F_DEBUG, MPPI_F_GRAD, MPPI_F_SHIFT, Batch, Controller,
                        MppiError, Params, check, cvar, free_energy, header_functions, last_error, lib, make_params,
-                       normals, philox)
+                       normals, philox, step_noalloc)
 
 __all__ = ["Batch", "Controller", "MppiError", "Params", "check", "cvar", "header_functions", "last_error", "lib",
-           "make_params", "normals", "philox", "free_energy", "MPPI_F_DEBUG", "MPPI_F_SHIFT",
+           "make_params", "normals", "philox", "free_energy", "step_noalloc", "MPPI_F_DEBUG", "MPPI_F_SHIFT",
            "MPPI_F_ALLOW_ZERO_NOISE", "MPPI_F_GRAD"]

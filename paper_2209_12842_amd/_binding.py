@@ -72,6 +72,8 @@ def lib():
         L.mppi_create.restype = ctypes.c_int
         L.mppi_step.argtypes = [V, P(F), V, U32, P(F), V]
         L.mppi_step.restype = ctypes.c_int
+        L.mppi_step_noalloc.argtypes = [P(Params), V, P(F), V, U32, V, V]
+        L.mppi_step_noalloc.restype = ctypes.c_int
         L.mppi_grad.argtypes = [V, P(F), V, U32, V, V, V]
         L.mppi_grad.restype = I32
         L.mppi_destroy.argtypes = [V]
@@ -352,6 +354,36 @@ def cvar(L, alpha: float, B: float = 1.0):
     check(lib().mppi_cvar(ctypes.c_void_p(L.data_ptr()), L.shape[0], L.shape[1], float(alpha), float(B),
                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(_stream_ptr(L.device))))
     return out
+
+
+def step_noalloc(params: dict, obstacles, x0, V, step_idx: int, u0=None, allow_zero_noise: bool = False) -> None:
+    """One step through mppi_step_noalloc (no handle, no workspace: the
+    library's static scratch).  obstacles: n x 3 float32 CUDA tensor (or None
+    for none), V: T x 2 float32 CUDA tensor updated in place, u0: None or a
+    2-float CUDA tensor receiving the first command.  Enqueues on the current
+    stream of V's device and returns."""
+    torch = _torch()
+    if not (V.is_cuda and V.dtype == torch.float32 and V.is_contiguous()):
+        raise ValueError("V must be a contiguous float32 CUDA tensor")
+    n_obs = 0
+    obs_ptr = None
+    if obstacles is not None:
+        if not (obstacles.is_cuda and obstacles.dtype == torch.float32 and obstacles.is_contiguous()
+                and obstacles.dim() == 2 and obstacles.shape[1] == 3):
+            raise ValueError("obstacles must be a contiguous (n, 3) float32 CUDA tensor")
+        n_obs = int(obstacles.shape[0])
+        obs_ptr = ctypes.c_void_p(obstacles.data_ptr()) if n_obs else None
+    if u0 is not None and not (u0.is_cuda and u0.dtype == torch.float32 and u0.numel() == 2 and u0.is_contiguous()):
+        raise ValueError("u0 must be a contiguous float32 CUDA tensor of 2 elements")
+    pr = make_params(params, n_obs, MPPI_F_ALLOW_ZERO_NOISE if allow_zero_noise else 0)
+    if V.numel() != 2 * pr.T:
+        raise ValueError("V must hold T x 2 elements")
+    x = (ctypes.c_float * 4)(*(float(v) for v in x0))
+    with torch.cuda.device(V.device):
+        check(lib().mppi_step_noalloc(ctypes.byref(pr), obs_ptr, x, ctypes.c_void_p(V.data_ptr()),
+                                      int(step_idx) & 0xFFFFFFFF,
+                                      ctypes.c_void_p(u0.data_ptr()) if u0 is not None else None,
+                                      ctypes.c_void_p(_stream_ptr(V.device))))
 
 
 class Batch:

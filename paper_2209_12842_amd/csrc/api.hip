@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -514,6 +515,115 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
         u0_host[0] = h->u0_pinned[0];
         u0_host[1] = h->u0_pinned[1];
     }
+    return MPPI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch memory of mppi_step_noalloc: the step's workspace (obstacle table,
+// sampled controls, per-sample costs, chunk partials, counters) in a static
+// device array, so that the call allocates nothing.  Each device that runs
+// the call holds its own copy until the process ends.  Host code uses only
+// the device address that hipGetSymbolAddress returns for the current device
+// (g_scratch_dev), never the array's name.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxScratchDevices];
+
+// The scratch's device address on device `dev` (looked up once per device,
+// with that device current).
+mppi_status scratch_address(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(MPPI_EUNSUPPORTED, "device %d is beyond the %d devices the scratch table covers", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_scratch_dev[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return MPPI_OK;
+}
+
+// Stages the caller's obstacles (n_obs x 3 floats) as the table's float4
+// entries and zeroes the update's counters, which must start at zero (a fill
+// kernel rather than a memset, so that the call can be captured in a graph).
+__global__ void k_noalloc_prep(const float* __restrict__ obs3, int n_obs, float4* __restrict__ obs4,
+                               unsigned* __restrict__ counter, unsigned* __restrict__ chunk_ctr, int G) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_obs) obs4[i] = make_float4(obs3[3 * i], obs3[3 * i + 1], obs3[3 * i + 2], 0.0f);
+    if (i < G) chunk_ctr[i] = 0u;
+    if (i == 0) *counter = 0u;
+}
+
+}  // namespace
+
+extern "C" {
+
+mppi_status mppi_step_noalloc(const mppi_params* p, const float* obstacles_dev, const float x0[4], float* V_dev,
+                              uint32_t step_idx, float* u0_dev, void* stream) {
+    if (!p) return fail(MPPI_EINVAL, "params is NULL");
+    mppi_status st = mppi_validate(p);
+    if (st != MPPI_OK) return st;
+    if (p->flags & (MPPI_F_DEBUG | MPPI_F_GRAD))
+        return fail(MPPI_EINVAL, "MPPI_F_DEBUG and MPPI_F_GRAD need a handle (mppi_create)");
+    if (p->n_obs > 0 && !obstacles_dev) return fail(MPPI_EINVAL, "obstacles_dev is NULL with n_obs > 0");
+    if (!x0) return fail(MPPI_EINVAL, "x0 is NULL");
+    if (!V_dev) return fail(MPPI_EINVAL, "V_dev is NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!finite(x0[i])) return fail(MPPI_EINVAL, "x0[%d] is not finite", i);
+    const Layout l = layout(p);
+    if (l.total > kScratchBytes)
+        return fail(MPPI_EUNSUPPORTED, "the step needs %zu B of scratch, more than the %zu B of mppi_step_noalloc",
+                    l.total, kScratchBytes);
+    int dev = 0;
+    st = check_device(&dev);
+    if (st != MPPI_OK) return st;
+    char* ws = nullptr;
+    st = scratch_address(dev, &ws);
+    if (st != MPPI_OK) return st;
+
+    const Geometry g = geometry(p);
+    int n_tail = 0, n_warm = 0;
+    derived_counts(p, &n_tail, &n_warm);
+    ramppi::StepConst c;
+    fill_static(&c, *p, g, n_tail, n_warm);
+    fill_dynamic(&c, *p, x0, step_idx);
+    c.u0_seq = 0;
+
+    ramppi::StepBuffers bufs;
+    bufs.obs = reinterpret_cast<const float4*>(ws + l.obs);
+    bufs.V = V_dev;
+    bufs.Vout = V_dev;
+    bufs.u = reinterpret_cast<float2*>(ws + l.u);
+    bufs.S = reinterpret_cast<float*>(ws + l.S);
+    bufs.cvar = reinterpret_cast<float*>(ws + l.cvar);
+    bufs.S_tilde = reinterpret_cast<float*>(ws + l.S_tilde);
+    bufs.w_hat = reinterpret_cast<float*>(ws + l.w_hat);
+    bufs.L = reinterpret_cast<float*>(ws + l.L);
+    bufs.part = reinterpret_cast<float*>(ws + l.part);
+    bufs.u0 = u0_dev ? u0_dev : reinterpret_cast<float*>(ws + l.u0);
+    bufs.counter = reinterpret_cast<unsigned*>(ws + l.counter);
+    bufs.u0_host = nullptr;
+    bufs.work = nullptr;
+    bufs.chunk_ctr = reinterpret_cast<unsigned*>(ws + l.chunk);
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n_prep = std::max(std::max(p->n_obs, g.G), 1);
+    hipLaunchKernelGGL(k_noalloc_prep, dim3((n_prep + 255) / 256), dim3(256), 0, s, obstacles_dev, p->n_obs,
+                       reinterpret_cast<float4*>(ws + l.obs), bufs.counter, bufs.chunk_ctr, g.G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "obstacle staging launch");
+    // always the two-launch form (rollouts, then the update): it needs no
+    // occupancy query and gives the same bits as the one-launch step
+    e = ramppi::launch_step(c, bufs, g.block, g.lds_rollout, g.G, g.lds_update, s, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
     return MPPI_OK;
 }
 
