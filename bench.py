@@ -37,7 +37,7 @@ line on stdout:
 
     python bench.py [--steps K] [--warmup W] [--workload c3|c2|c1|c4|p0]
 
-With --workload other than c3 the line carries that workload only.
+With --workload (c3 included) the line carries that workload only.
 
 Other legs (one JSON line each, not the default):
   --workload c5   batched serving: 64 independent controllers of uneven size
@@ -283,10 +283,11 @@ def main():
         return run_study(args, R, torch)
     if args.workload == "c5":
         return run_batch(args, R, torch)
-    if args.workload is None:
+    headline = args.workload is None
+    if headline:
         args.workload = "c3"
     out = run_plain(R, torch, args.workload, args.steps, args.warmup)
-    if args.workload == "c3":
+    if headline:
         # the latency configuration and the paper's own sample counts, as
         # extra keys beside the headline (their own warm-up and step counts)
         c2 = run_plain(R, torch, "c2", 200, 10)

@@ -29,15 +29,61 @@ constexpr uint32_t kCtrlWord = 0xFFFFFFFFu;
 // (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key
 // then advances by the two Weyl constants.
 // a ^ b ^ k in one instruction (gfx950's three-input bitwise operation with
-// the truth table of XOR3); k is the key word, the same in every lane.
+// the truth table of XOR3); k is the key word, the same in every lane, read
+// from a scalar register (xor3_key) or from a vector register that holds it
+// in every lane (xor3_vkey).
 __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
     uint32_t d;
     asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
     return d;
 }
 
-__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                               uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ uint32_t xor3_vkey(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "v"(k));
+    return d;
+}
+
+// A lane-uniform value copied into a vector register.  A VALU instruction of
+// gfx950 that reads a scalar register does not pair with a VALU instruction
+// of another wave in the same cycle (measured: an FMA with a scalar operand
+// takes about 4.7 SIMD clocks per wave, one with vector operands about 3),
+// so the constants that the rollout steps read at every step are kept in
+// vector registers.
+__device__ __forceinline__ float in_vgpr(float s) {
+    float v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t in_vgpr_u(uint32_t s) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
+// The keys of the fourth to the tenth round in vector registers (the rounds
+// before them XOR words that are still the same in every lane, on the
+// scalar unit).
+struct PhiloxVKeys {
+    uint32_t k0[7], k1[7];
+};
+
+__device__ __forceinline__ PhiloxVKeys philox_vkeys(uint32_t k0, uint32_t k1) {
+    PhiloxVKeys v;
+#pragma unroll
+    for (int r = 0; r < 7; ++r) {
+        v.k0[r] = in_vgpr_u(k0 + (uint32_t)(r + 3) * kPhiloxW0);
+        v.k1[r] = in_vgpr_u(k1 + (uint32_t)(r + 3) * kPhiloxW1);
+    }
+    return v;
+}
+
+// kVecKeys: the keys of rounds 4 to 10 come from vk (vector registers),
+// otherwise from the scalar key schedule.  Both give the same words.
+template <bool kVecKeys>
+__device__ __forceinline__ uint4 philox4x32_10_rounds(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                      uint32_t k0, uint32_t k1, const PhiloxVKeys* vk) {
     {
         // first round in plain C: counter words that are the same in every
         // lane (the time step, the call index) then stay on the scalar unit
@@ -58,8 +104,21 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
         const uint64_t p1 = (uint64_t)c2 * kPhiloxM1;
         const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
         const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
-        const uint32_t n0 = xor3_key(hi1, c1, k0);
-        const uint32_t n2 = xor3_key(hi0, c3, k1);
+        // the second and third rounds still see words that are the same in
+        // every lane (from the first round's scalar words): plain XORs let
+        // the compiler fold the key into them on the scalar unit; from the
+        // fourth round on every word differs per lane
+        uint32_t n0, n2;
+        if (r < 3) {
+            n0 = hi1 ^ c1 ^ k0;
+            n2 = hi0 ^ c3 ^ k1;
+        } else if (kVecKeys) {
+            n0 = xor3_vkey(hi1, c1, vk->k0[r - 3]);
+            n2 = xor3_vkey(hi0, c3, vk->k1[r - 3]);
+        } else {
+            n0 = xor3_key(hi1, c1, k0);
+            n2 = xor3_key(hi0, c3, k1);
+        }
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -70,12 +129,28 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+    return philox4x32_10_rounds<false>(c0, c1, c2, c3, k0, k1, nullptr);
+}
+
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1, const PhiloxVKeys& vk) {
+    return philox4x32_10_rounds<true>(c0, c1, c2, c3, k0, k1, &vk);
+}
+
 // uint32 -> (0, 1): ((r >> 9) + 1/2) 2^-23, exact in FP32.  Built as the
 // float 1 + (r >> 9) 2^-23 (exponent bits 0x7F over the top 23 bits of r, one
 // funnel shift) minus (1 - 2^-24), a subtraction that is exact (both lie in
 // [1/2, 2] of each other and the result needs 24 significant bits).
 __device__ __forceinline__ float uniform01(uint32_t r) {
     return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, r, 9u)) - 0x1.fffffep-1f;
+}
+
+// The same map with the exponent word 0x7F passed in (a vector register
+// holding it keeps the shift from reading a scalar register).
+__device__ __forceinline__ float uniform01(uint32_t r, uint32_t exp_word) {
+    return __uint_as_float(__builtin_amdgcn_alignbit(exp_word, r, 9u)) - 0x1.fffffep-1f;
 }
 
 // Two standard normals from two uniforms (Box-Muller).  The hardware
@@ -134,6 +209,54 @@ struct State {
     float x, y, psi, v;  // position in the local frame
 };
 
+// The step constants with the fields that the disturbed rollout steps read
+// (dynamics, running cost, disturbance scales) in vector registers.
+__device__ __forceinline__ StepConst with_vector_constants(const StepConst& c) {
+    StepConst v = c;
+    v.dt = in_vgpr(c.dt);
+    v.tox = in_vgpr(c.tox);
+    v.toy = in_vgpr(c.toy);
+    v.inv_a = in_vgpr(c.inv_a);
+    v.inv_b = in_vgpr(c.inv_b);
+    v.g_a = in_vgpr(c.g_a);
+    v.g_b = in_vgpr(c.g_b);
+    v.c_dev = in_vgpr(c.c_dev);
+    v.c_v = in_vgpr(c.c_v);
+    v.v_ref = in_vgpr(c.v_ref);
+    v.sw0 = in_vgpr(c.sw0);
+    v.sw1 = in_vgpr(c.sw1);
+    v.sw2 = in_vgpr(c.sw2);
+    v.sw3 = in_vgpr(c.sw3);
+    return v;
+}
+
+// The disturbed successor F(x, u) + w (Eq. 6) of a state s that already
+// holds F(x, u), for the disturbance of Philox words r.  In the Gaussian form
+// each component's scale and its Box-Muller factor fold into the addition
+// (w_x = sqrt(Sigma_w,x) rad cos(2 pi u1) added by one fused multiply-add
+// onto x); the other forms add w as it is.  Every rollout that needs the
+// disturbed dynamics (the risk costs and the gradient's recomputation) uses
+// this, so all of them see the same states.
+// exp_word: 0x7F, the exponent word of uniform01 (in a vector register in
+// the hot loop).
+template <int kNoise>
+__device__ __forceinline__ State disturbed_successor(const StepConst& c, uint4 r, const State& s,
+                                                     uint32_t exp_word = 0x7Fu) {
+    if (kNoise == 0) {
+        const float u1 = uniform01(r.y, exp_word), u3 = uniform01(r.w, exp_word);
+        const float ra =
+            __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(r.x, exp_word)));
+        const float rb =
+            __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(r.z, exp_word)));
+        return State{__fmaf_rn(c.sw0 * ra, __builtin_amdgcn_cosf(u1), s.x),
+                     __fmaf_rn(c.sw1 * ra, __builtin_amdgcn_sinf(u1), s.y),
+                     __fmaf_rn(c.sw2 * rb, __builtin_amdgcn_cosf(u3), s.psi),
+                     __fmaf_rn(c.sw3 * rb, __builtin_amdgcn_sinf(u3), s.v)};
+    }
+    const float4 w = disturbance<kNoise>(c, r);
+    return State{s.x + w.x, s.y + w.y, s.psi + w.z, s.v + w.w};
+}
+
 template <int kNoise>
 __device__ __forceinline__ float4 disturbance(const StepConst& c, uint4 r) {
     if (kNoise == 0) {
@@ -181,11 +304,12 @@ __device__ __forceinline__ float tan_steer(float d) {
     return __builtin_amdgcn_sinf(r) * __builtin_amdgcn_rcpf(__builtin_amdgcn_cosf(r));
 }
 
-// Track and speed terms of q: c_dev e^2 + c_v (v - v_ref)^2 [+ c_bdry mu_bdry
-// when kBdry; the rollouts pick the instantiation once, so that a run of
-// steps holds no branch].
+// Track and speed terms of q added to the running sum acc: acc + c_dev e^2 +
+// c_v (v - v_ref)^2 [+ c_bdry mu_bdry when kBdry; the rollouts pick the
+// instantiation once, so that a run of steps holds no branch].  Each term
+// is folded into the sum by its own fused multiply-add.
 template <bool kBdry>
-__device__ __forceinline__ float smooth_cost_k(const StepConst& c, const State& s) {
+__device__ __forceinline__ float smooth_cost_acc(const StepConst& c, const State& s, float acc) {
     const float X = s.x + c.tox;
     const float Y = s.y + c.toy;
     const float xa = X * c.inv_a;
@@ -195,18 +319,15 @@ __device__ __forceinline__ float smooth_cost_k(const StepConst& c, const State& 
     const float gy = Y * c.g_b;   // 2 Y / b^2
     const float gn2 = fmaxf(__fmaf_rn(gx, gx, gy * gy), 1e-24f);
     const float dv = s.v - c.v_ref;
-    float q = __fmaf_rn(c.c_v * dv, dv, c.c_dev * (G * G * __builtin_amdgcn_rcpf(gn2)));
+    acc = __fmaf_rn(c.c_dev * G, G * __builtin_amdgcn_rcpf(gn2), acc);
+    acc = __fmaf_rn(c.c_v * dv, dv, acc);
     if (kBdry) {
         const float e = G * rsqrtf(gn2);
         const float d = c.hw - fabsf(e);
         const float mu = fmaxf(0.0f, atanf(-100.0f * d) * 0.318309886183790671538f + 0.5f);
-        q = __fmaf_rn(c.c_bdry, mu, q);
+        acc = __fmaf_rn(c.c_bdry, mu, acc);
     }
-    return q;
-}
-
-__device__ __forceinline__ float smooth_cost(const StepConst& c, const State& s) {
-    return c.use_bdry ? smooth_cost_k<true>(c, s) : smooth_cost_k<false>(c, s);
+    return acc;
 }
 
 // Obstacle test (Eq. 22) on the table of a step (obstacle_entry): the point
@@ -282,9 +403,21 @@ __device__ __forceinline__ void cull_group(const float4 e, float bx0, float bx1,
         cand &= cand - 1;
         n_cand += n;
         const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
+        // the S tests give lane masks; only the lanes inside the disc at
+        // some point add them to their counts, and the wave skips the
+        // additions when there are none (most candidates of the box test
+        // are near misses)
+        bool hit[S];
+        bool any = false;
 #pragma unroll
-        for (int u = 0; u < S; ++u)
-            if (u < n) cnt += (__fmaf_rn(a, px[u], __fmaf_rn(b, py[u], rho[u])) < z) ? 1 : 0;
+        for (int u = 0; u < S; ++u) {
+            hit[u] = (u < n) && (__fmaf_rn(a, px[u], __fmaf_rn(b, py[u], rho[u])) < z);
+            any = any || hit[u];
+        }
+        if (any) {
+#pragma unroll
+            for (int u = 0; u < S; ++u) cnt += hit[u] ? 1 : 0;
+        }
     }
 }
 

@@ -84,13 +84,12 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
         slot = a.u[(size_t)min(t + kGradAhead, T - 1) * K + k];
         bicycle_step(s, c.dt * uu.x, tan_steer(uu.y) * c.inv_wheelbase, c.dt);
         const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-        const float4 w = disturbance<kNoise>(c, r);
+        const State n = disturbed_successor<kNoise>(c, r, s);
         const bool add = disturbed && t + 1 < T;
-        const float nx = s.x + w.x, ny = s.y + w.y, np = s.psi + w.z, nv = s.v + w.w;
-        s.x = add ? nx : s.x;
-        s.y = add ? ny : s.y;
-        s.psi = add ? np : s.psi;
-        s.v = add ? nv : s.v;
+        s.x = add ? n.x : s.x;
+        s.y = add ? n.y : s.y;
+        s.psi = add ? n.psi : s.psi;
+        s.v = add ? n.v : s.v;
     };
     for (int tb = 0; tb < T; tb += kGradAhead) {
         if (tb + kGradAhead <= T) {

@@ -170,7 +170,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         auto step = [&](auto bdry, int t, float& px, float& py) {
             const float2 u = sample_control(c, vsh, kc, t);
             if (act) u_out[(size_t)t * c.K + k] = u;
-            acc += smooth_cost_k<decltype(bdry)::value>(c, s);
+            acc = smooth_cost_acc<decltype(bdry)::value>(c, s, acc);
             px = s.x;
             py = s.y;
             const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
@@ -244,6 +244,9 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     const bool active = (sl < spb) && (k < c.K);
     float L = 0.0f;
     {
+        const StepConst cv = with_vector_constants(c);
+        const PhiloxVKeys vk = philox_vkeys(c.key0, c.key1);
+        const uint32_t exp_word = in_vgpr_u(0x7Fu);
         // every lane runs a rollout (the obstacle test works on whole waves);
         // lanes past the workgroup's last sample repeat its controls, and the
         // results of inactive lanes are dropped
@@ -255,18 +258,14 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         // one disturbed state step: running cost at x_t, then (t < T - 1; the
         // last draw cannot reach the risk cost) x_{t+1}
         auto step = [&](auto bdry, int t, bool advance, float& px, float& py) {
-            acc += smooth_cost_k<decltype(bdry)::value>(c, s);
+            acc = smooth_cost_acc<decltype(bdry)::value>(cv, s, acc);
             px = s.x;
             py = s.y;
             if (advance) {
-                const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1);
-                const float4 w = disturbance<kNoise>(c, r);
+                const uint4 r = philox4x32_10((uint32_t)t, (uint32_t)m, (uint32_t)k, c.step_idx, c.key0, c.key1, vk);
                 const float2 cc = ck[t];
-                bicycle_step(s, cc.x, cc.y, c.dt);
-                s.x += w.x;
-                s.y += w.y;
-                s.psi += w.z;
-                s.v += w.w;
+                bicycle_step(s, cc.x, cc.y, cv.dt);
+                s = disturbed_successor<kNoise>(cv, r, s, exp_word);
             }
         };
         for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points

@@ -7,13 +7,15 @@ held fixed (Eq. 2 with the modified costs of Eq. 16 and the weights of
 Eq. 17).  Tolerances, from the FP32 arithmetic of the device:
   J       |dJ| <= 1e-4 max(|J|, 1): J is a soft minimum of the S~, each within
           the rollout bound 1e-4 relative;
-  dJ/dV   max |dg| <= (2e-3 + 2 dS) max |g|, where dS is the spread
+  dJ/dV   max |dg| <= (2e-4 + 2 dS) max |g|, where dS is the spread
           (max - min) of the signed FP32 errors of the modified costs S~_k
           over the weighted samples, in units of lambda.  The weights depend
           only on differences of the S~ (a common shift cancels in Eq. 17),
           so each log-weight moves by at most dS (first order) and each
           weight by at most about 2 dS of itself; the per-sample adjoints
-          carry FP32 rounding over T steps (2e-3).  The whole factor is capped
+          carry FP32 rounding over T steps (2e-4: a few units in the last
+          place per step over up to 50 steps, with margin; the largest
+          error measured over every case is 2.3e-6).  The whole factor is capped
           at 1e-2: a case whose measured dS would allow more fails.  When a
           single sample carries the weight (dS = 0), the gradient is that
           sample's adjoint and is also checked element by element.
@@ -39,7 +41,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU hosts
 import paper_2209_12842_amd as R  # noqa: E402
 
 J_RTOL = 1e-4
-G_RTOL = 2e-3
+G_RTOL = 2e-4
 
 
 def _log(msg):
@@ -90,7 +92,7 @@ def _compare(p, dev, J_ref, g_ref, o, tag=""):
     # the normalised weights of the forward pass match the oracle's
     assert np.abs(dev["w_hat"] - o["w_hat"]).max() <= 2.0 * dS + 1e-5
     if int(wk.sum()) == 1 and float(o["w_hat"][~wk].sum()) <= 1e-6:
-        # one sample's adjoint: each component to 2e-3 relative, above a
+        # one sample's adjoint: each component to 2e-4 relative, above a
         # floor of 1e-2 max|g| for components that nearly cancel
         e = np.abs(dev["g"] - g_ref) / np.maximum(np.abs(g_ref), 1e-2 * gmax)
         _log("  single weighted sample: max elementwise rel %.2e" % e.max())
