@@ -230,6 +230,23 @@ __device__ __forceinline__ StepConst with_vector_constants(const StepConst& c) {
     return v;
 }
 
+// with_vector_constants plus the fields of the nominal rollouts' steps
+// (control sampling, clamp and control cost).
+__device__ __forceinline__ StepConst with_vector_constants_nominal(const StepConst& c) {
+    StepConst v = with_vector_constants(c);
+    v.se0 = in_vgpr(c.se0);
+    v.se1 = in_vgpr(c.se1);
+    v.u_lo0 = in_vgpr(c.u_lo0);
+    v.u_lo1 = in_vgpr(c.u_lo1);
+    v.u_hi0 = in_vgpr(c.u_hi0);
+    v.u_hi1 = in_vgpr(c.u_hi1);
+    v.inv_var0 = in_vgpr(c.inv_var0);
+    v.inv_var1 = in_vgpr(c.inv_var1);
+    v.gamma = in_vgpr(c.gamma);
+    v.inv_wheelbase = in_vgpr(c.inv_wheelbase);
+    return v;
+}
+
 // The disturbed successor F(x, u) + w (Eq. 6) of a state s that already
 // holds F(x, u), for the disturbance of Philox words r.  In the Gaussian form
 // each component's scale and its Box-Muller factor fold into the addition
@@ -391,9 +408,9 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
 // rollout: the table does not change within a step); later groups are read
 // from LDS at every call.
 template <int S>
-__device__ __forceinline__ void cull_group(const float4 e, float bx0, float bx1, float by0, float by1, float p2,
-                                           const float (&px)[S], const float (&py)[S], const float (&rho)[S], int n,
-                                           int& cnt, int& n_cand) {
+__device__ __forceinline__ void cull_group(const float4 e, const float4* grp, float bx0, float bx1, float by0,
+                                           float by1, float p2, const float (&px)[S], const float (&py)[S],
+                                           const float (&rho)[S], int n, int& cnt, int& n_cand) {
     const float cx = -0.5f * e.x, cy = -0.5f * e.y;
     const float dx = fmaxf(fmaxf(bx0 - cx, cx - bx1), 0.0f);
     const float dy = fmaxf(fmaxf(by0 - cy, cy - by1), 0.0f);
@@ -402,7 +419,11 @@ __device__ __forceinline__ void cull_group(const float4 e, float bx0, float bx1,
         const int j = __builtin_ctzll(cand);
         cand &= cand - 1;
         n_cand += n;
-        const float a = lane_f32(e.x, j), b = lane_f32(e.y, j), z = lane_f32(e.z, j);
+        // the candidate's entry read from LDS at one address for the whole
+        // wave: it arrives in vector registers, so that the tests below
+        // read no scalar register (see in_vgpr)
+        const float4 ej = grp[j];
+        const float a = ej.x, b = ej.y, z = ej.z;
         // the S tests give lane masks; only the lanes inside the disc at
         // some point add them to their counts, and the wave skips the
         // additions when there are none (most candidates of the box test
@@ -425,8 +446,8 @@ __device__ __forceinline__ void cull_group(const float4 e, float bx0, float bx1,
 template <int S>
 __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float4 e0,
                                                     const float (&px)[S], const float (&py)[S], int n, int& n_cand) {
-    const float xc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px[0])));
-    const float yc = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py[0])));
+    const float xc = in_vgpr(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px[0]))));
+    const float yc = in_vgpr(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py[0]))));
     float mx = fabsf(px[0] - xc), my = fabsf(py[0] - yc);
     float rho[S];
 #pragma unroll
@@ -444,18 +465,18 @@ __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ o
     const float p2 = 3.0517578125e-05f * __fmaf_rn(ax, ax, ay * ay);  // 2^-15 P^2
     const int lane = threadIdx.x & 63;
     int cnt = 0;
-    cull_group<S>(e0, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+    cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
     for (int g = 1; g < n_grp; ++g)
-        cull_group<S>(otab[g * 64 + lane], bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+        cull_group<S>(otab[g * 64 + lane], otab + g * 64, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
     return cnt;
 }
 
 // Sampled control (Eq. 2b-2c with the warm / zero-mean rule of Algorithm 1):
 // u = clamp(base + sqrt(Sigma_eps) z, u_lo, u_hi), base = v_t for k < n_warm.
-__device__ __forceinline__ float2 sample_control(const StepConst& c, const float* __restrict__ V, int k, int t) {
-    const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1);
+__device__ __forceinline__ float2 sample_control_from(const StepConst& c, const float* __restrict__ V, int k, int t,
+                                                     uint4 r, uint32_t exp_word) {
     float z0, z1;
-    box_muller(uniform01(r.x), uniform01(r.y), z0, z1);
+    box_muller(uniform01(r.x, exp_word), uniform01(r.y, exp_word), z0, z1);
     // every lane reads v_t (t < T, in bounds) and warm samples keep it: a
     // select, not a branch
     const bool warm = k < c.n_warm;
@@ -467,6 +488,19 @@ __device__ __forceinline__ float2 sample_control(const StepConst& c, const float
     a = fminf(fmaxf(a, c.u_lo0), c.u_hi0);
     d = fminf(fmaxf(d, c.u_lo1), c.u_hi1);
     return make_float2(a, d);
+}
+
+__device__ __forceinline__ float2 sample_control(const StepConst& c, const float* __restrict__ V, int k, int t) {
+    const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1);
+    return sample_control_from(c, V, k, t, r, 0x7Fu);
+}
+
+// The same draw with the Philox keys and the exponent word in vector
+// registers (the nominal rollouts' steps).
+__device__ __forceinline__ float2 sample_control(const StepConst& c, const float* __restrict__ V, int k, int t,
+                                                 const PhiloxVKeys& vk, uint32_t exp_word) {
+    const uint4 r = philox4x32_10((uint32_t)t, kCtrlWord, (uint32_t)k, c.step_idx, c.key0, c.key1, vk);
+    return sample_control_from(c, V, k, t, r, exp_word);
 }
 
 // Angle wrap to (-pi, pi].

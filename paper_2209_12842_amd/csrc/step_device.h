@@ -164,18 +164,21 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f, ctrl = 0.0f;
         int cnt = 0;
+        const StepConst cn = with_vector_constants_nominal(c);
+        const PhiloxVKeys vk = philox_vkeys(c.key0, c.key1);
+        const uint32_t exp_word = in_vgpr_u(0x7Fu);
         // one nominal state step: the sampled control, running and control
         // costs at x_t (the control cost is summed in every case and used
         // when asked, so that the step holds no branch), then x_{t+1}
         auto step = [&](auto bdry, int t, float& px, float& py) {
-            const float2 u = sample_control(c, vsh, kc, t);
+            const float2 u = sample_control(cn, vsh, kc, t, vk, exp_word);
             if (act) u_out[(size_t)t * c.K + k] = u;
-            acc = smooth_cost_acc<decltype(bdry)::value>(c, s, acc);
+            acc = smooth_cost_acc<decltype(bdry)::value>(cn, s, acc);
             px = s.x;
             py = s.y;
-            const float term = __fmaf_rn(vsh[2 * t] * c.inv_var0, u.x, vsh[2 * t + 1] * c.inv_var1 * u.y);
-            ctrl = __fmaf_rn(c.gamma, term, ctrl);
-            bicycle_step(s, c.dt * u.x, tan_steer(u.y) * c.inv_wheelbase, c.dt);
+            const float term = __fmaf_rn(vsh[2 * t] * cn.inv_var0, u.x, vsh[2 * t + 1] * cn.inv_var1 * u.y);
+            ctrl = __fmaf_rn(cn.gamma, term, ctrl);
+            bicycle_step(s, cn.dt * u.x, tan_steer(u.y) * cn.inv_wheelbase, cn.dt);
         };
         for (int t0 = 0; t0 < T; t0 += kCullSteps) {  // the obstacle test runs once per kCullSteps points
             float px[kCullSteps], py[kCullSteps];
