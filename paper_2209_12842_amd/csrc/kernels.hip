@@ -23,12 +23,12 @@
 namespace ramppi {
 
 template <int kNoise, bool kFuse>
-__global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __restrict__ obs,
-                                                  const float* __restrict__ V, float2* __restrict__ u_out,
-                                                  float* __restrict__ S_out, float* __restrict__ cvar_out,
-                                                  float* __restrict__ L_out, int* __restrict__ ranks,
-                                                  int* __restrict__ tail_idx, unsigned long long* __restrict__ work,
-                                                  const FuseArgs* __restrict__ fa) {
+__device__ __forceinline__ void rollout_launch_body(const StepConst& c, const float4* __restrict__ obs,
+                                                    const float* __restrict__ V, float2* __restrict__ u_out,
+                                                    float* __restrict__ S_out, float* __restrict__ cvar_out,
+                                                    float* __restrict__ L_out, int* __restrict__ ranks,
+                                                    int* __restrict__ tail_idx, unsigned long long* __restrict__ work,
+                                                    const FuseArgs* __restrict__ fa) {
     extern __shared__ float2 smem[];
     rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx, work);
     if constexpr (kFuse) {
@@ -41,6 +41,32 @@ __global__ void __launch_bounds__(1024) k_rollout(StepConst c, const float4* __r
         fused_update(c, f, blockIdx.x, S_out, cvar_out, u_out, const_cast<float*>(V),
                      reinterpret_cast<float*>(smem), red, &flag_sh, fin_sh);
     }
+}
+
+// The rollouts of the two-launch step (the large grids, which hold many
+// waves per SIMD).  Compiled for five waves per SIMD: the register budget
+// then holds the per-step constants and keys in vector registers with room
+// for a fifth wave (measured on the large step: 0.71 -> 0.68 ms; the
+// one-launch kernel, whose grid holds two or three waves per SIMD, runs
+// faster with the registers it needs).
+template <int kNoise>
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
+    k_rollout(StepConst c, const float4* __restrict__ obs, const float* __restrict__ V, float2* __restrict__ u_out,
+              float* __restrict__ S_out, float* __restrict__ cvar_out, float* __restrict__ L_out,
+              int* __restrict__ ranks, int* __restrict__ tail_idx, unsigned long long* __restrict__ work,
+              const FuseArgs* __restrict__ fa) {
+    rollout_launch_body<kNoise, false>(c, obs, V, u_out, S_out, cvar_out, L_out, ranks, tail_idx, work, fa);
+}
+
+// The one-launch step: rollouts, then the update in the workgroups that
+// finish each chunk.
+template <int kNoise>
+__global__ void __launch_bounds__(1024)
+    k_rollout_fused(StepConst c, const float4* __restrict__ obs, const float* __restrict__ V,
+                    float2* __restrict__ u_out, float* __restrict__ S_out, float* __restrict__ cvar_out,
+                    float* __restrict__ L_out, int* __restrict__ ranks, int* __restrict__ tail_idx,
+                    unsigned long long* __restrict__ work, const FuseArgs* __restrict__ fa) {
+    rollout_launch_body<kNoise, true>(c, obs, V, u_out, S_out, cvar_out, L_out, ranks, tail_idx, work, fa);
 }
 
 // Persistent serving: the one-launch step in a loop, one iteration per
@@ -143,15 +169,27 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
 template <bool kFuse>
 static void launch_rollout_t(const StepConst& c, const StepBuffers& b, dim3 grid, int block, size_t lds,
                              hipStream_t stream, int* ranks, int* tail_idx, const FuseArgs* fa) {
-    if (c.noise_kind == 1)
-        hipLaunchKernelGGL((k_rollout<1, kFuse>), grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
-                           b.L, ranks, tail_idx, b.work, fa);
-    else if (c.noise_kind == 2)
-        hipLaunchKernelGGL((k_rollout<2, kFuse>), grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
-                           b.L, ranks, tail_idx, b.work, fa);
-    else
-        hipLaunchKernelGGL((k_rollout<0, kFuse>), grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
-                           b.L, ranks, tail_idx, b.work, fa);
+    if constexpr (kFuse) {
+        if (c.noise_kind == 1)
+            hipLaunchKernelGGL(k_rollout_fused<1>, grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
+                               b.L, ranks, tail_idx, b.work, fa);
+        else if (c.noise_kind == 2)
+            hipLaunchKernelGGL(k_rollout_fused<2>, grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
+                               b.L, ranks, tail_idx, b.work, fa);
+        else
+            hipLaunchKernelGGL(k_rollout_fused<0>, grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar,
+                               b.L, ranks, tail_idx, b.work, fa);
+    } else {
+        if (c.noise_kind == 1)
+            hipLaunchKernelGGL(k_rollout<1>, grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
+                               ranks, tail_idx, b.work, fa);
+        else if (c.noise_kind == 2)
+            hipLaunchKernelGGL(k_rollout<2>, grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
+                               ranks, tail_idx, b.work, fa);
+        else
+            hipLaunchKernelGGL(k_rollout<0>, grid, dim3(block), lds, stream, c, b.obs, b.V, b.u, b.S, b.cvar, b.L,
+                               ranks, tail_idx, b.work, fa);
+    }
 }
 
 hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int n_dist_wg,
@@ -163,10 +201,10 @@ hipError_t launch_rollout(const StepConst& c, const StepBuffers& b, int block, s
 
 hipError_t fused_rollout_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu) {
     if (noise_kind == 1)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<1, true>, block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout_fused<1>, block, lds);
     if (noise_kind == 2)
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<2, true>, block, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout<0, true>, block, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout_fused<2>, block, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_rollout_fused<0>, block, lds);
 }
 
 hipError_t serve_capacity(int noise_kind, int block, size_t lds, int* blocks_per_cu) {
