@@ -368,8 +368,9 @@ __device__ __forceinline__ float seg_min_256(const float* v, float* red) {
 //     sum_b scale_b Z_b; then V (shifted when asked), the first command and,
 //     in debug mode, w_hat; in gradient mode J, every w_hat and the list of
 //     samples of non-zero weight instead, V unchanged.
-// LDS (dynamic, ush): w[256] | slice sums [parts][2T], then for the merge
-// v[256] | scale[G] | zb[G] | vp[2T] (update_lds_bytes).
+// LDS (dynamic, ush): w[256] | slice sums [parts][2T] | nzpos[257] |
+// nzlist[256], then for the merge v[256] | scale[G] | zb[G] | vp[2T]
+// (update_lds_bytes).
 template <int kB>
 __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int parts, const float* __restrict__ S,
                                              const float* __restrict__ cvar, const float2* __restrict__ u,
@@ -379,20 +380,12 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     const int tid = threadIdx.x, nt = blockDim.x;
     float* wsh = ush;
     float* psh = wsh + 256;
+    int* nzpos = reinterpret_cast<int*>(psh + (size_t)parts * 2 * T);  // 257
+    int* nzlist = nzpos + 257;                                          // 256
     const int k0 = b * 256;
     const int n = min(256, K - k0);
     const int stride = 2 + 2 * T;
     const int slice = (n + parts - 1) / parts;
-
-    // The first batch of this thread's first slice of controls does not
-    // depend on the weights: its loads are issued before them.
-    float2 pre[kB];
-    const bool has_pre = tid < T * parts && (tid % parts) * slice + kB <= min(n, (tid % parts + 1) * slice);
-    if (has_pre) {
-        const float2* ut = u + (size_t)(tid / parts) * K + k0 + (tid % parts) * slice;
-#pragma unroll
-        for (int i = 0; i < kB; ++i) pre[i] = ut[i];
-    }
 
     // 1. modified costs and chunk weights
     for (int i = tid; i < 256; i += nt) {
@@ -409,45 +402,75 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     for (int i = tid; i < 256; i += nt) wsh[i] = (i < n) ? expf(-(wsh[i] - beta_b) / c.lambda) : 0.0f;
     const float Z_b = seg_sum_256(wsh, red);  // also publishes wsh
 
-    // 2. weighted control sums over slices of the chunk
+    // The samples of non-zero weight in index order (exp underflows to an
+    // exact zero once a cost exceeds the chunk's minimum by about 104
+    // lambda): nzlist holds them, nzpos[k] how many come before sample k.
+    // A zero weight adds 0 * u, which leaves a sum exactly as it is, so the
+    // sums below skip those samples and still give the bits of the full
+    // sums.
+    {
+        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+        for (int sg = wv; sg < 4; sg += nw) {
+            const int k = 64 * sg + lane;
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(wsh[k] != 0.0f);
+            nzpos[k] = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+            if (lane == 0) red[sg] = __int_as_float(__builtin_popcountll(bal));
+        }
+        __syncthreads();
+        const int c0 = __float_as_int(red[0]), c1 = __float_as_int(red[1]), c2 = __float_as_int(red[2]);
+        const int c3 = __float_as_int(red[3]);
+        for (int k = tid; k < 256; k += nt) {
+            const int sg = k >> 6;
+            const int off = (sg > 0 ? c0 : 0) + (sg > 1 ? c1 : 0) + (sg > 2 ? c2 : 0);
+            const int q = off + nzpos[k];
+            nzpos[k] = q;
+            if (wsh[k] != 0.0f) nzlist[q] = k;
+        }
+        if (tid == 0) nzpos[256] = c0 + c1 + c2 + c3;
+        __syncthreads();
+    }
+
+    // 2. weighted control sums over slices of the chunk, in index order
     for (int idx = tid; idx < T * parts; idx += nt) {
         const int t = idx / parts;  // neighbouring lanes read the slices of one row
         const int pr = idx % parts;
         const int ka = pr * slice, kb = min(n, ka + slice);
         const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
-        int k = ka;
-        if (idx == tid && has_pre) {  // the prefetched batch, summed in the same order
-#pragma unroll
-            for (int i = 0; i < kB; ++i) {
-                ax = __fmaf_rn(wsh[k + i], pre[i].x, ax);
-                ay = __fmaf_rn(wsh[k + i], pre[i].y, ay);
-            }
-            k += kB;
-        }
-        for (; k + kB <= kb; k += kB) {  // kB loads in flight, then the sums in order
-            float2 uu[kB];
-#pragma unroll
-            for (int i = 0; i < kB; ++i) uu[i] = ut[k + i];
-#pragma unroll
-            for (int i = 0; i < kB; ++i) {
-                ax = __fmaf_rn(wsh[k + i], uu[i].x, ax);
-                ay = __fmaf_rn(wsh[k + i], uu[i].y, ay);
-            }
-        }
-        if (k < kb) {  // the rest in one more round; padding terms are 0 * 0 and leave the sums as they are
+        int q = ka < kb ? nzpos[ka] : 0;
+        const int qb = ka < kb ? nzpos[kb] : 0;
+        for (; q + kB <= qb; q += kB) {  // kB loads in flight, then the sums in order
             float2 uu[kB];
             float ww[kB];
 #pragma unroll
             for (int i = 0; i < kB; ++i) {
-                const bool in = k + i < kb;
-                uu[i] = in ? ut[k + i] : make_float2(0.0f, 0.0f);
-                ww[i] = in ? wsh[k + i] : 0.0f;
+                const int k = nzlist[q + i];
+                ww[i] = wsh[k];
+                uu[i] = ut[k];
             }
 #pragma unroll
             for (int i = 0; i < kB; ++i) {
                 ax = __fmaf_rn(ww[i], uu[i].x, ax);
                 ay = __fmaf_rn(ww[i], uu[i].y, ay);
+            }
+        }
+        if (q < qb) {  // the rest in one more round
+            float2 uu[kB];
+            float ww[kB];
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                const bool in = q + i < qb;
+                const int k = in ? nzlist[q + i] : 0;
+                ww[i] = in ? wsh[k] : 0.0f;
+                uu[i] = in ? ut[k] : make_float2(0.0f, 0.0f);
+            }
+#pragma unroll
+            for (int i = 0; i < kB; ++i) {
+                if (q + i < qb) {
+                    ax = __fmaf_rn(ww[i], uu[i].x, ax);
+                    ay = __fmaf_rn(ww[i], uu[i].y, ay);
+                }
             }
         }
         psh[(size_t)pr * 2 * T + 2 * t] = ax;
@@ -639,13 +662,18 @@ __device__ __forceinline__ void update_merge_single(const StepConst& c, const fl
 __device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned target, int* flag_sh) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // a release increment; only the last arrival acquires (the others
+        // leave their caches as they are)
+        const unsigned done = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         *flag_sh = (done == target - 1u);
-        if (*flag_sh) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (*flag_sh) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     __syncthreads();
     const bool last = *flag_sh != 0;
-    if (last) __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return last;
 }
 
@@ -770,9 +798,12 @@ __device__ __forceinline__ void fused_update(const StepConst& c, const FuseArgs&
         int nf = 0;
         for (int b = lo >> 8; b <= (hi - 1) >> 8; ++b) {
             const unsigned target = chunk_contributors(c, b, (int)blockDim.x);
+            // a release increment; only the workgroup that completes the
+            // chunk acquires, so the others keep their caches
             const unsigned done =
-                __hip_atomic_fetch_add(&f.chunk_ctr[b], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&f.chunk_ctr[b], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (done == target - 1u) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 __hip_atomic_store(&f.chunk_ctr[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 fin_sh[nf++] = b;
             }
@@ -782,7 +813,7 @@ __device__ __forceinline__ void fused_update(const StepConst& c, const FuseArgs&
     __syncthreads();
     const int nf = fin_sh[7];
     if (nf == 0) return;
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int i = 0; i < nf; ++i) {
         update_chunk<kFuseBatch>(c, fin_sh[i], f.parts, S, cvar, u, f.S_tilde, f.part, ush, red);
         if (f.G == 1)  // its own record, visible to the workgroup after update_chunk's barrier
