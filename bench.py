@@ -16,11 +16,13 @@ line on stdout:
                brute-force-equivalent rate (every obstacle tested at every
                state) is given beside it.  When the whole grid is resident
                the step is one launch whose duration also covers the update
-               (about 3 % of the FLOPs, not counted); valu_issue gives the
-               VALU instructions per SIMD per clock (counted by rocprofv3,
-               profiles/k_rollout_valu_counters.md) over the same duration
-               against the wave64 issue ceiling of 0.25, which is what
-               bounds the kernel
+               (about 3 % of the FLOPs, not counted); valu_issue gives, over
+               the same duration and from the committed rocprofv3 counters
+               (profiles/k_rollout_valu_counters.md), the VALU
+               instructions per SIMD per clock, the wave-cycles spent in
+               VALU instructions per SIMD-cycle (about 1: the vector ALU is
+               what bounds the kernel) and the share of them that two
+               waves issued together
   serving      the same loop (same number of steps) through a persistent
                serving session (mppi_serve_*: one resident launch, one
                request per step): rollout-steps/s, ms per step and latency
@@ -162,17 +164,19 @@ def measured_traffic(workload: str):
     return float(vals["fetch bytes per launch"]) + float(vals["write bytes per launch"])
 
 
-# MI355X: 256 CUs x 4 SIMDs at a 2.4 GHz engine clock; a wave64 VALU
-# instruction occupies its SIMD for at least 4 clocks.
+# MI355X: 256 CUs x 4 SIMDs at a 2.4 GHz engine clock.  A SIMD issues a
+# wave64 FP32 VALU instruction in two clocks when the instructions of two
+# waves pair in one four-clock cycle (the FP32 vector peak, 157.3 TFLOP/s),
+# in four when they do not; transcendental and 64-bit integer instructions
+# take longer (measured: about 8 and 6 clocks per wave).
 N_SIMD = 1024
 CLOCK_HZ = 2.4e9
-VALU_ISSUE_CEILING = 0.25
 
 
-def measured_valu(workload: str):
-    """VALU instructions per rollout launch (SQ_INSTS_VALU, whole device) from
-    the committed counter summary (profiles/k_rollout_valu_counters.md), or
-    None when there is none for the workload or the kernel sources changed."""
+def _counter_record(workload: str):
+    """Fields of the committed VALU counter summary
+    (profiles/k_rollout_valu_counters.md) when the kernel sources still hash
+    to the recorded value, else None."""
     path = os.path.join(ROOT, "profiles", "k_rollout_valu_counters.md")
     if not os.path.exists(path):
         return None
@@ -183,19 +187,40 @@ def measured_valu(workload: str):
             vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel sources sha256") != kernel_sources_sha256():
         return None
+    return vals
+
+
+def measured_valu(workload: str):
+    """VALU instructions per rollout launch (SQ_INSTS_VALU, whole device) from
+    the committed counter summary, or None when there is none for the
+    workload or the kernel sources changed."""
+    vals = _counter_record(workload)
+    if vals is None:
+        return None
     v = vals.get("%s VALU instructions per launch" % workload)
     return float(v) if v is not None else None
 
 
 def valu_issue(workload: str, seconds_per_launch: float):
-    """VALU instructions issued per SIMD per clock over the measured launch
-    duration, against the wave64 issue ceiling; None without a record."""
+    """How the rollout kernel uses its SIMDs over the measured launch
+    duration, from the committed counters: VALU instructions issued per SIMD
+    per clock; valu_busy, the wave-cycles spent in VALU instructions
+    (SQ_ACTIVE_INST_VALU, summed over the waves) per SIMD-cycle; and the share
+    of those cycles in which two waves issued together (SQ_ACTIVE_INST_VALU2).
+    None without a record."""
+    vals = _counter_record(workload)
     n = measured_valu(workload)
-    if n is None or not seconds_per_launch > 0:
+    if vals is None or n is None or not seconds_per_launch > 0:
         return None
-    rate = n / (seconds_per_launch * CLOCK_HZ * N_SIMD)
-    return {"insts_per_launch": n, "per_simd_per_clock": rate, "ceiling": VALU_ISSUE_CEILING,
-            "frac": rate / VALU_ISSUE_CEILING}
+    simd_cycles = seconds_per_launch * CLOCK_HZ * N_SIMD
+    out = {"insts_per_launch": n, "per_simd_per_clock": n / simd_cycles}
+    act = vals.get("%s active VALU quad-cycles per launch" % workload)
+    dual = vals.get("%s dual-issue quad-cycles per launch" % workload)
+    if act is not None:
+        out["valu_busy"] = 4.0 * float(act) / simd_cycles
+        if dual is not None:
+            out["dual_issue_frac"] = float(dual) / float(act)
+    return out
 
 
 def plant_step(x, u, dt, wb, w):

@@ -50,8 +50,9 @@ def test_valu_record_is_used_only_for_the_kernel_it_measured(monkeypatch):
     assert bench.measured_valu("c1") is None  # nothing measured
     r = bench.valu_issue("c3", 0.8e-3)
     if r is not None:
-        assert abs(r["per_simd_per_clock"] - r["insts_per_launch"] / (0.8e-3 * 2.4e9 * 1024)) < 1e-12
-        assert r["frac"] == r["per_simd_per_clock"] / 0.25
+        cycles = 0.8e-3 * 2.4e9 * 1024
+        assert abs(r["per_simd_per_clock"] - r["insts_per_launch"] / cycles) < 1e-12
+        assert 0.0 < r["valu_busy"] < 2.0 and 0.0 <= r["dual_issue_frac"] <= 1.0
     assert bench.valu_issue("c3", 0.0) is None
     monkeypatch.setattr(bench, "kernel_sources_sha256", lambda: "0" * 64)
     assert bench.measured_valu("c2") is None and bench.valu_issue("c3", 1e-3) is None
