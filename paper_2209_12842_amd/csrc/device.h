@@ -424,20 +424,20 @@ __device__ __forceinline__ void cull_group(const float4 e, const float4* grp, fl
         // read no scalar register (see in_vgpr)
         const float4 ej = grp[j];
         const float a = ej.x, b = ej.y, z = ej.z;
-        // the S tests give lane masks; only the lanes inside the disc at
-        // some point add them to their counts, and the wave skips the
-        // additions when there are none (most candidates of the box test
-        // are near misses)
-        bool hit[S];
-        bool any = false;
+        // one compare of the smallest of the S test values tells whether the
+        // lane is inside the disc at any point (points past n repeat a valid
+        // point, so they add no false alarm); only then are the points
+        // compared one by one and counted, and the wave skips that when no
+        // lane is inside (most candidates of the box test are near misses)
+        float d[S];
 #pragma unroll
-        for (int u = 0; u < S; ++u) {
-            hit[u] = (u < n) && (__fmaf_rn(a, px[u], __fmaf_rn(b, py[u], rho[u])) < z);
-            any = any || hit[u];
-        }
-        if (any) {
+        for (int u = 0; u < S; ++u) d[u] = __fmaf_rn(a, px[u], __fmaf_rn(b, py[u], rho[u]));
+        float dmin = d[0];
 #pragma unroll
-            for (int u = 0; u < S; ++u) cnt += hit[u] ? 1 : 0;
+        for (int u = 1; u < S; ++u) dmin = fminf(dmin, d[u]);
+        if (dmin < z) {
+#pragma unroll
+            for (int u = 0; u < S; ++u) cnt += (u < n && d[u] < z) ? 1 : 0;
         }
     }
 }

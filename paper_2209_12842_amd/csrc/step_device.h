@@ -387,49 +387,51 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     const int stride = 2 + 2 * T;
     const int slice = (n + parts - 1) / parts;
 
-    // 1. modified costs and chunk weights
-    for (int i = tid; i < 256; i += nt) {
-        float st = __builtin_inff();
-        if (i < n) {
-            const float cv = cvar[k0 + i];
-            const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
-            st = S[k0 + i] + jc;                               // Eq. 16
-            S_tilde[k0 + i] = st;
+    // 1. modified costs, the chunk's minimum beta_b, its weights and their
+    // sum Z_b, and the samples of non-zero weight, all by the first wave:
+    // lane l holds samples l, l + 64, l + 128 and l + 192 (the four 64-value
+    // segments of seg_min_256 / seg_sum_256, reduced by the same butterflies
+    // and combined in the same order, so the bits are theirs), and no
+    // barrier separates the steps.  The samples of non-zero weight go to
+    // nzlist in index order (exp underflows to an exact zero once a cost
+    // exceeds the chunk's minimum by about 104 lambda), nzpos[k] counting
+    // how many come before sample k.  A zero weight adds 0 * u, which leaves
+    // a sum exactly as it is, so the sums below skip those samples and still
+    // give the bits of the full sums.
+    float beta_b = 0.0f, Z_b = 0.0f;
+    if (tid < 64) {
+        float w[4];
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) {
+            const int i = 64 * sg + tid;
+            float st = __builtin_inff();
+            if (i < n) {
+                const float cv = cvar[k0 + i];
+                const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
+                st = S[k0 + i] + jc;                               // Eq. 16
+                S_tilde[k0 + i] = st;
+            }
+            w[sg] = st;
         }
-        wsh[i] = st;
-    }
-    const float beta_b = seg_min_256(wsh, red);
-    for (int i = tid; i < 256; i += nt) wsh[i] = (i < n) ? expf(-(wsh[i] - beta_b) / c.lambda) : 0.0f;
-    const float Z_b = seg_sum_256(wsh, red);  // also publishes wsh
-
-    // The samples of non-zero weight in index order (exp underflows to an
-    // exact zero once a cost exceeds the chunk's minimum by about 104
-    // lambda): nzlist holds them, nzpos[k] how many come before sample k.
-    // A zero weight adds 0 * u, which leaves a sum exactly as it is, so the
-    // sums below skip those samples and still give the bits of the full
-    // sums.
-    {
-        const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
-        for (int sg = wv; sg < 4; sg += nw) {
-            const int k = 64 * sg + lane;
-            const uint64_t bal = __builtin_amdgcn_ballot_w64(wsh[k] != 0.0f);
-            nzpos[k] = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-            if (lane == 0) red[sg] = __int_as_float(__builtin_popcountll(bal));
-        }
-        __syncthreads();
-        const int c0 = __float_as_int(red[0]), c1 = __float_as_int(red[1]), c2 = __float_as_int(red[2]);
-        const int c3 = __float_as_int(red[3]);
-        for (int k = tid; k < 256; k += nt) {
-            const int sg = k >> 6;
-            const int off = (sg > 0 ? c0 : 0) + (sg > 1 ? c1 : 0) + (sg > 2 ? c2 : 0);
-            const int q = off + nzpos[k];
+        beta_b = wave_min(fminf(fminf(w[0], w[1]), fminf(w[2], w[3])));  // a minimum: exact in any order
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) w[sg] = (64 * sg + tid < n) ? expf(-(w[sg] - beta_b) / c.lambda) : 0.0f;
+        Z_b = (wave_sum(w[0]) + wave_sum(w[1])) + (wave_sum(w[2]) + wave_sum(w[3]));
+        int off = 0;
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) {
+            const int k = 64 * sg + tid;
+            const uint64_t bal = __builtin_amdgcn_ballot_w64(w[sg] != 0.0f);
+            const int q = off + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
             nzpos[k] = q;
-            if (wsh[k] != 0.0f) nzlist[q] = k;
+            if (w[sg] != 0.0f) nzlist[q] = k;
+            wsh[k] = w[sg];
+            off += __builtin_popcountll(bal);
         }
-        if (tid == 0) nzpos[256] = c0 + c1 + c2 + c3;
-        __syncthreads();
+        if (tid == 0) nzpos[256] = off;
     }
+    __syncthreads();  // wsh, nzpos and nzlist published
 
     // 2. weighted control sums over slices of the chunk, in index order
     for (int idx = tid; idx < T * parts; idx += nt) {
@@ -573,46 +575,74 @@ __device__ __forceinline__ void update_merge(const StepConst& c, int G, const fl
     float* scale = vsh + 256;
     float* zb = scale + G;
     float* vp = zb + G;
+    // rows of the weighted sums loaded before beta and Z are known
+    constexpr int kP = kB > 8 ? kB : 8;
 
-    // The first batch of the weighted sums (thread j < 2T) does not depend
-    // on beta or Z: its loads are issued first.
-    float pre[kB];
-    const bool has_pre = tid < 2 * T && kB <= G;
+    // The first kP rows of the weighted sums (thread j < 2T) do not depend
+    // on beta or Z: their loads are issued first.
+    float pre[kP];
+    const int n_pre = G < kP ? G : kP;
+    const bool has_pre = tid < 2 * T;
     if (has_pre) {
 #pragma unroll
-        for (int i = 0; i < kB; ++i) pre[i] = part[(size_t)i * stride + 2 + tid];
+        for (int i = 0; i < kP; ++i) pre[i] = i < n_pre ? part[(size_t)i * stride + 2 + tid] : 0.0f;
     }
-    // virtual thread i (of 256) takes chunks i, i + 256, ...; beta_b and Z_b
-    // are read once and kept in LDS
-    for (int i = tid; i < 256; i += nt) {
-        float m = __builtin_inff();
-        for (int bb = i; bb < G; bb += 256) {
-            const float be = part[(size_t)bb * stride];
-            scale[bb] = be;
-            zb[bb] = part[(size_t)bb * stride + 1];
-            m = fminf(m, be);
+    float beta, Z;
+    if (G <= 64) {
+        // one wave, chunk b in lane b: the minimum (exact in any order), the
+        // scales, and Z by the butterfly of seg_sum_256's first segment (its
+        // other three segments hold zeros, whose sums add nothing to a
+        // positive Z, so the bits are the same); one barrier publishes them
+        if (tid < 64) {
+            const bool in = tid < G;
+            const float be = in ? part[(size_t)tid * stride] : __builtin_inff();
+            const float z0 = in ? part[(size_t)tid * stride + 1] : 0.0f;
+            const float bmin = wave_min(be);
+            const float sc = in ? expf(-(be - bmin) / c.lambda) : 0.0f;
+            const float zs = wave_sum(__fmaf_rn(z0, sc, 0.0f));
+            if (in) scale[tid] = sc;
+            if (tid == 0) {
+                red[0] = bmin;
+                red[1] = zs;
+            }
         }
-        vsh[i] = m;
-    }
-    const float beta = seg_min_256(vsh, red);  // also publishes scale (beta_b) and zb
-    for (int i = tid; i < 256; i += nt) {
-        float z = 0.0f;
-        for (int bb = i; bb < G; bb += 256) {
-            const float sc = expf(-(scale[bb] - beta) / c.lambda);
-            scale[bb] = sc;
-            z = __fmaf_rn(zb[bb], sc, z);
+        __syncthreads();
+        beta = red[0];
+        Z = red[1];
+    } else {
+        // virtual thread i (of 256) takes chunks i, i + 256, ...; beta_b and
+        // Z_b are read once and kept in LDS
+        for (int i = tid; i < 256; i += nt) {
+            float m = __builtin_inff();
+            for (int bb = i; bb < G; bb += 256) {
+                const float be = part[(size_t)bb * stride];
+                scale[bb] = be;
+                zb[bb] = part[(size_t)bb * stride + 1];
+                m = fminf(m, be);
+            }
+            vsh[i] = m;
         }
-        vsh[i] = z;
+        beta = seg_min_256(vsh, red);  // also publishes scale (beta_b) and zb
+        for (int i = tid; i < 256; i += nt) {
+            float z = 0.0f;
+            for (int bb = i; bb < G; bb += 256) {
+                const float sc = expf(-(scale[bb] - beta) / c.lambda);
+                scale[bb] = sc;
+                z = __fmaf_rn(zb[bb], sc, z);
+            }
+            vsh[i] = z;
+        }
+        Z = seg_sum_256(vsh, red);  // also publishes scale
     }
-    const float Z = seg_sum_256(vsh, red);  // also publishes scale
     const float invZ = 1.0f / Z;
     for (int j = tid; j < 2 * T; j += nt) {
         float acc = 0.0f;
         int bb = 0;
-        if (j == tid && has_pre) {  // the prefetched batch, summed in the same order
+        if (j == tid && has_pre) {  // the prefetched rows, summed in the same order
 #pragma unroll
-            for (int i = 0; i < kB; ++i) acc = __fmaf_rn(pre[i], scale[i], acc);
-            bb = kB;
+            for (int i = 0; i < kP; ++i)
+                if (i < n_pre) acc = __fmaf_rn(pre[i], scale[i], acc);
+            bb = n_pre;
         }
         for (; bb + kB <= G; bb += kB) {  // kB loads in flight, then the sums in order
             float pv[kB];
