@@ -81,7 +81,9 @@ enum {
  *   eta          share of zero-mean samples in [0, 1] (Algorithm 1).
  *   A, B, C_u    CVaR penalty gain, risk-scaling factor, CVaR bound (Eq. 14-19).
  *   c_bdry, c_obs, c_dev, c_v, v_ref   running-cost weights (Eq. 20-22):
- *                q = c_bdry mu_bdry + c_obs mu_obs + c_dev e^2 + c_v (v - v_ref)^2.
+ *                q = c_bdry mu_bdry + c_obs mu_obs + c_dev e^2 + c_v (v - v_ref)^2;
+ *                all finite, c_v >= 0 (the speed term is formed as the square
+ *                of sqrt(c_v) (v - v_ref)).
  *   c4, c5       terminal cost phi = c4 - c5 s(x_T) (Eq. 23).
  *   track        elliptic centreline: centre (ox, oy), semi-axes (a, b) > 0,
  *                half width; e is the signed Sampson distance to it.
@@ -126,7 +128,9 @@ mppi_status mppi_validate(const mppi_params *p);
 size_t mppi_workspace_bytes(const mppi_params *p);
 
 /* Creates a controller.  obstacles_host: n_obs x 3 floats (cx, cy, r), r > 0,
- * copied into the workspace on `stream` (may be NULL when n_obs == 0).
+ * copied into the workspace on `stream` (may be NULL when n_obs == 0); the
+ * copy is ordered by angle around the obstacles' centroid, which speeds up
+ * the obstacle test and changes no result (the cost counts every hit).
  * workspace_dev: caller-owned device memory of at least
  * mppi_workspace_bytes(p) bytes, 256-byte aligned, which must outlive the
  * handle.  On success *out receives the handle.  Synchronises `stream` once. */
@@ -135,7 +139,9 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
                         void *stream, mppi_handle **out);
 
 /* One RA-MPPI iteration (Algorithm 1, one pass of its loop).
- *   x0        host, 4 floats: the measured state (finite).
+ *   x0        host, 4 floats: the measured state (finite).  A heading of
+ *             magnitude above 100 rad is reduced modulo 2 pi (in FP64) before
+ *             the rollouts start from it.
  *   V_dev     device, T x 2 floats row-major: in, the mean sequence V; out, V+
  *             (Eq. 4), shifted when MPPI_F_SHIFT is set.
  *   step_idx  call counter; it is the fourth Philox counter word, so the same

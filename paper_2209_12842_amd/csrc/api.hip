@@ -48,7 +48,36 @@ bool finite(float v) { return std::isfinite(v); }
 // means of the workgroup's samples, then the obstacle table in groups of 64.
 size_t rollout_lds_bytes(int spb, const mppi_params* p) {
     if ((int64_t)spb * p->T > (1 << 24)) return SIZE_MAX;  // far beyond any LDS
-    return 4 * (size_t)ramppi::rollout_otab_offset(spb, p->T, p->M) + 16 * 64 * (size_t)ramppi::rollout_n_grp(p->n_obs);
+    // the table (64 entries per group), then 64 group boxes
+    const size_t n_grp = (size_t)ramppi::rollout_n_grp(p->n_obs);
+    return 4 * (size_t)ramppi::rollout_otab_offset(spb, p->T, p->M) + 16 * 64 * n_grp + (n_grp > 1 ? 16 * 64 : 0);
+}
+
+// The order in which the obstacles are staged: by angle around their
+// centroid, so that each group of 64 consecutive table entries covers one
+// stretch of a track-like layout and a wave's box meets few groups (the
+// group skip of the broad phase).  The hit count is a sum over all
+// obstacles, so the order changes no result.
+std::vector<int> obstacle_order(const float* o, int n) {
+    std::vector<int> idx(n > 0 ? n : 0);
+    if (n <= 64) {  // one group: the order does not matter
+        for (int i = 0; i < n; ++i) idx[i] = i;
+        return idx;
+    }
+    double mx = 0.0, my = 0.0;
+    for (int i = 0; i < n; ++i) {
+        mx += o[3 * i];
+        my += o[3 * i + 1];
+    }
+    mx /= n;
+    my /= n;
+    std::vector<double> ang(n);
+    for (int i = 0; i < n; ++i) {
+        idx[i] = i;
+        ang[i] = std::atan2((double)o[3 * i + 1] - my, (double)o[3 * i] - mx);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return ang[a] < ang[b]; });
+    return idx;
 }
 
 // Mapped pinned bytes per handle: the first command (2 floats), its
@@ -191,6 +220,8 @@ void fill_static(ramppi::StepConst* cp, const mppi_params& p, const Geometry& g,
     c.c_dev = p.c_dev;
     c.c_v = p.c_v;
     c.v_ref = p.v_ref;
+    c.rc_v = (float)std::sqrt((double)p.c_v);
+    c.rc_v_ref = (float)(std::sqrt((double)p.c_v) * (double)p.v_ref);
     c.c4 = p.c4;
     c.c5 = p.c5;
     c.use_bdry = p.c_bdry != 0.0f;
@@ -218,7 +249,7 @@ void fill_dynamic(ramppi::StepConst* cp, const mppi_params& p, const float x0[4]
     c.toy = x0[1] - p.track[1];
     c.theta0 = (float)std::atan2(((double)x0[1] - p.track[1]) / (double)p.track[3],
                                  ((double)x0[0] - p.track[0]) / (double)p.track[2]);
-    c.psi0 = x0[2];
+    c.psi0 = ramppi::start_heading(x0[2]);
     c.v0 = x0[3];
     c.step_idx = step_idx;
 }
@@ -319,6 +350,7 @@ mppi_status mppi_validate(const mppi_params* p) {
     const float w[7] = {p->c_bdry, p->c_obs, p->c_dev, p->c_v, p->v_ref, p->c4, p->c5};
     for (int i = 0; i < 7; ++i)
         if (!finite(w[i])) return fail(MPPI_EINVAL, "cost weights must be finite");
+    if (!(p->c_v >= 0)) return fail(MPPI_EINVAL, "c_v must be >= 0");
     if (!(finite(p->track[0]) && finite(p->track[1]))) return fail(MPPI_EINVAL, "track centre must be finite");
     if (!(finite(p->track[2]) && p->track[2] > 0 && finite(p->track[3]) && p->track[3] > 0))
         return fail(MPPI_EINVAL, "track semi-axes must be finite and > 0");
@@ -400,10 +432,11 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     std::vector<float> staged(4 * (size_t)(p->n_obs > 0 ? p->n_obs : 1), 0.0f);
+    const std::vector<int> order = obstacle_order(obstacles_host, p->n_obs);
     for (int i = 0; i < p->n_obs; ++i) {
-        staged[4 * i + 0] = obstacles_host[3 * i + 0];
-        staged[4 * i + 1] = obstacles_host[3 * i + 1];
-        staged[4 * i + 2] = obstacles_host[3 * i + 2];
+        staged[4 * i + 0] = obstacles_host[3 * order[i] + 0];
+        staged[4 * i + 1] = obstacles_host[3 * order[i] + 1];
+        staged[4 * i + 2] = obstacles_host[3 * order[i] + 2];
     }
     e = hipMemcpyAsync(h->ws + l.obs, staged.data(), 16 * (size_t)p->n_obs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.counter, 0, 4, s);
@@ -1177,8 +1210,9 @@ mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* cons
         }
         for (int ch = 0; ch < g.G; ++ch) uitems.push_back(make_int2(i, ch));
         std::vector<float> staged(4 * (size_t)(p[i].n_obs > 0 ? p[i].n_obs : 1), 0.0f);
+        const std::vector<int> order = obstacle_order(obstacles_host[i], p[i].n_obs);
         for (int j = 0; j < p[i].n_obs; ++j)
-            for (int q = 0; q < 3; ++q) staged[4 * j + q] = obstacles_host[i][3 * j + q];
+            for (int q = 0; q < 3; ++q) staged[4 * j + q] = obstacles_host[i][3 * order[j] + q];
         if (e == hipSuccess && p[i].n_obs > 0)
             e = hipMemcpyAsync(base + l.obs, staged.data(), 16 * (size_t)p[i].n_obs, hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipMemsetAsync(base + l.counter, 0, 4, s);

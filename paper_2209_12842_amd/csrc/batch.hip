@@ -28,7 +28,7 @@ __device__ __forceinline__ void set_dynamic(StepConst& c, const BatchCtl& b, con
     c.toy = in.x0[1] - b.track[1];
     c.theta0 = (float)atan2(((double)in.x0[1] - (double)b.track[1]) / (double)b.track[3],
                             ((double)in.x0[0] - (double)b.track[0]) / (double)b.track[2]);
-    c.psi0 = in.x0[2];
+    c.psi0 = start_heading(in.x0[2]);
     c.v0 = in.x0[3];
     c.step_idx = in.step_idx;
 }

@@ -193,6 +193,7 @@ struct StepConst {
     float gamma, inv_var0, inv_var1;
     float A, B, C_u, lambda;
     float c_bdry, c_obs, c_dev, c_v, v_ref, c4, c5;
+    float rc_v, rc_v_ref;  // sqrt(c_v) and sqrt(c_v) v_ref: the speed term as (rc_v v - rc_v_ref)^2
     // track: offsets of the local frame from the ellipse centre, and shape
     float tox, toy, inv_a, inv_b, g_a, g_b, hw, half_ab;
     float theta0;        // ellipse angle of the start point
@@ -221,8 +222,8 @@ __device__ __forceinline__ StepConst with_vector_constants(const StepConst& c) {
     v.g_a = in_vgpr(c.g_a);
     v.g_b = in_vgpr(c.g_b);
     v.c_dev = in_vgpr(c.c_dev);
-    v.c_v = in_vgpr(c.c_v);
-    v.v_ref = in_vgpr(c.v_ref);
+    v.rc_v = in_vgpr(c.rc_v);
+    v.rc_v_ref = in_vgpr(c.rc_v_ref);
     v.sw0 = in_vgpr(c.sw0);
     v.sw1 = in_vgpr(c.sw1);
     v.sw2 = in_vgpr(c.sw2);
@@ -291,12 +292,28 @@ __device__ __forceinline__ float4 disturbance(const StepConst& c, uint4 r) {
     }
 }
 
+// Headings beyond this magnitude (radians) are reduced modulo 2 pi before a
+// rollout starts (start_heading), so that every heading a rollout reaches
+// stays well inside the input range of the hardware sine and cosine.
+constexpr double kMaxStartHeading = 100.0;
+
+// The start heading of a rollout: x0's heading, reduced modulo 2 pi (in FP64,
+// exactly) when its magnitude exceeds kMaxStartHeading.  The host and the
+// batched path's prep kernel both call this, so they agree bit for bit.
+__host__ __device__ __forceinline__ float start_heading(float psi) {
+    if (fabs((double)psi) <= kMaxStartHeading) return psi;
+    return (float)remainder((double)psi, 6.283185307179586476925);
+}
+
 // Forward-Euler bicycle step: da = dt a, kappa = tan(delta) / wheelbase.
-// The heading is turned into revolutions and reduced to [-1/2, 1/2] for the
-// hardware sine and cosine.
+// The hardware sine and cosine take the heading in revolutions as it is:
+// they reduce it themselves, with the same largest error (1.25e-7 against
+// FP64 over every float of 1/4 <= |r| < 64 revolutions) as after an explicit
+// reduction to [-1/2, 1/2], which would cost two more instructions per step.
+// A rollout's heading stays within about 15 rad of its start heading, so
+// |r| < 64 whenever |psi0| <= kMaxStartHeading.
 __device__ __forceinline__ void bicycle_step(State& s, float da, float kappa, float dt) {
-    float r = s.psi * 0.159154943091895335769f;
-    r = r - rintf(r);
+    const float r = s.psi * 0.159154943091895335769f;
     const float sn = __builtin_amdgcn_sinf(r);
     const float cs = __builtin_amdgcn_cosf(r);
     const float dv = dt * s.v;
@@ -335,9 +352,9 @@ __device__ __forceinline__ float smooth_cost_acc(const StepConst& c, const State
     const float gx = X * c.g_a;   // 2 X / a^2
     const float gy = Y * c.g_b;   // 2 Y / b^2
     const float gn2 = fmaxf(__fmaf_rn(gx, gx, gy * gy), 1e-24f);
-    const float dv = s.v - c.v_ref;
+    const float dv = __fmaf_rn(c.rc_v, s.v, -c.rc_v_ref);  // sqrt(c_v) (v - v_ref)
     acc = __fmaf_rn(c.c_dev * G, G * __builtin_amdgcn_rcpf(gn2), acc);
-    acc = __fmaf_rn(c.c_v * dv, dv, acc);
+    acc = __fmaf_rn(dv, dv, acc);
     if (kBdry) {
         const float e = G * rsqrtf(gn2);
         const float d = c.hw - fabsf(e);
@@ -352,21 +369,16 @@ __device__ __forceinline__ float smooth_cost_acc(const StepConst& c, const State
 // two FMAs on rho = |p|^2 and one compare.
 
 // Wave-wide maximum of a 32-bit unsigned value over all 64 lanes (every lane
-// active): rows of 16 lanes reduce with DPP lane permutations, row broadcasts
-// carry the row results up to the last lane, which is read into an SGPR.
-// The result is wave-uniform.  Non-negative floats order like their bit patterns, so it
+// active): rows of 16 lanes reduce with DPP lane permutations; then rows 1
+// and 3 take in the last lane of the row before (row_bcast:15) and rows 2
+// and 3 the last lane of row 1 (row_bcast:31), each one DPP maximum whose
+// row mask leaves the other rows as they are, and lane 63, which then holds
+// the wave's maximum, is read into a scalar register.  The result is
+// wave-uniform.  Non-negative floats order like their bit patterns, so it
 // also serves for the maximum of |x|.
 template <int kCtrl>
 __device__ __forceinline__ uint32_t dpp_max_u32(uint32_t v) {
     const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xF, 0xF, false);
-    return v > o ? v : o;
-}
-
-// Rows 1 and 3 (row_bcast:15), then rows 2 and 3 (row_bcast:31), take in
-// the last lane of the row before; other rows keep their values.
-template <int kCtrl, int kRowMask>
-__device__ __forceinline__ uint32_t dpp_max_rows_u32(uint32_t v) {
-    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, kCtrl, kRowMask, 0xF, false);
     return v > o ? v : o;
 }
 
@@ -375,8 +387,15 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
     v = dpp_max_u32<0x4E>(v);   // quad_perm [2,3,0,1]
     v = dpp_max_u32<0x141>(v);  // row_half_mirror
     v = dpp_max_u32<0x140>(v);  // row_mirror: every lane holds its row's maximum
-    v = dpp_max_rows_u32<0x142, 0xA>(v);  // row_bcast:15
-    v = dpp_max_rows_u32<0x143, 0xC>(v);  // row_bcast:31: lane 63 holds the wave's maximum
+    // written out because the compiler builds each broadcast step from a
+    // move, a DPP move and a maximum; the s_nop gives the two wait states a
+    // DPP read of a VGPR that a VALU instruction has just written needs
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+        "s_nop 1\n\t"
+        "v_max_u32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf"
+        : "+v"(v));
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
@@ -393,7 +412,8 @@ __device__ __forceinline__ float lane_f32(float v, int lane) {
 // the lanes' points from it along x and y, against every disc, lane j
 // testing entry 64 g + j of the table staged in LDS (otab, n_grp groups of
 // 64): d2 = squared distance from the disc centre to the box, candidate iff
-// d2 < q + 2^-15 P^2, where P^2 = (|xc| + Rx)^2 + (|yc| + Ry)^2 bounds |p|^2
+// d2 - 2^-15 P^2 < q (evaluated as dx^2 + (dy^2 - 2^-15 P^2), two fused
+// multiply-adds), where P^2 = (|xc| + Rx)^2 + (|yc| + Ry)^2 bounds |p|^2
 // over the box.  The margin exceeds the rounding error of both this test and
 // the exact test (each a few units in the last place of r^2 + |c|^2 + |p|^2,
 // the box edges a few units in the last place of P) by more than twenty
@@ -414,7 +434,7 @@ __device__ __forceinline__ void cull_group(const float4 e, const float4* grp, fl
     const float cx = -0.5f * e.x, cy = -0.5f * e.y;
     const float dx = fmaxf(fmaxf(bx0 - cx, cx - bx1), 0.0f);
     const float dy = fmaxf(fmaxf(by0 - cy, cy - by1), 0.0f);
-    uint64_t cand = __builtin_amdgcn_ballot_w64(__fmaf_rn(dx, dx, dy * dy) < e.w + p2);
+    uint64_t cand = __builtin_amdgcn_ballot_w64(__fmaf_rn(dx, dx, __fmaf_rn(dy, dy, -p2)) < e.w);
     while (cand) {
         const int j = __builtin_ctzll(cand);
         cand &= cand - 1;
@@ -442,10 +462,30 @@ __device__ __forceinline__ void cull_group(const float4 e, const float4* grp, fl
     }
 }
 
-// px, py: the S points (entries past n repeat a valid point).
+// Group skip of the broad phase (tables of more than one group).  Each group
+// of 64 table entries has a bounding box: the union of its discs' squares
+// |x - cx|, |y - cy| <= sqrt(q), widened by kGroupPad on every side
+// (group_bounds).  A wave box that does not meet it is farther than
+// sqrt(q) + kGroupPad from every centre of the group in x or in y, so each
+// disc's squared distance exceeds (sqrt(q) + kGroupPad)^2 > q + 2^-15 P^2
+// as long as 2^-7.5 P <= kGroupPad - 0.086 (P <= 256 m; beyond that every
+// group is tested): the broad phase would reject the whole group, and the
+// wave skips its test.  With the table sorted by angle around the
+// obstacles' centroid (the host does that), a box along a track meets one or
+// two groups.  The boxes are tested four compares per box for all groups at
+// once: lane g holds group g's box (gb), lanes past the last group an empty
+// one.
+constexpr float kGroupPad = 1.5f;
+constexpr float kGroupPadP2 = 65536.0f;  // P^2 up to which kGroupPad covers the broad-phase margin
+
+// px, py: the S points (entries past n repeat a valid point).  gbox: the 64
+// group boxes in LDS (see kGroupPad; boxes past n_grp meet nothing), read at
+// every call rather than held in registers through the rollout; n_grp == 1
+// tests the one group directly.
 template <int S>
-__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, int n_grp, float4 e0,
-                                                    const float (&px)[S], const float (&py)[S], int n, int& n_cand) {
+__device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, const float4* gbox, int n_grp,
+                                                    float4 e0, const float (&px)[S], const float (&py)[S], int n,
+                                                    int& n_cand) {
     const float xc = in_vgpr(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px[0]))));
     const float yc = in_vgpr(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py[0]))));
     float mx = fabsf(px[0] - xc), my = fabsf(py[0] - yc);
@@ -462,12 +502,28 @@ __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ o
     const float ry = __uint_as_float(wave_max_u32(__float_as_uint(my)));
     const float bx0 = xc - rx, bx1 = xc + rx, by0 = yc - ry, by1 = yc + ry;
     const float ax = fabsf(xc) + rx, ay = fabsf(yc) + ry;
-    const float p2 = 3.0517578125e-05f * __fmaf_rn(ax, ax, ay * ay);  // 2^-15 P^2
+    const float P2 = __fmaf_rn(ax, ax, ay * ay);
+    const float p2 = 3.0517578125e-05f * P2;  // 2^-15 P^2
     const int lane = threadIdx.x & 63;
     int cnt = 0;
-    cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
-    for (int g = 1; g < n_grp; ++g)
+    if (n_grp == 1) {
+        cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+        return cnt;
+    }
+    const float4 gb = gbox[lane];  // 64 entries, empty past n_grp
+    // four compare masks combined on the scalar unit
+    uint64_t gm = __builtin_amdgcn_ballot_w64(gb.x <= bx1) & __builtin_amdgcn_ballot_w64(gb.y >= bx0) &
+                  __builtin_amdgcn_ballot_w64(gb.z <= by1) & __builtin_amdgcn_ballot_w64(gb.w >= by0);
+    // (P2 is the same in every lane: the ballot makes that known, so that
+    // the mask stays in scalar registers)
+    if (__builtin_amdgcn_ballot_w64(P2 > kGroupPadP2) != 0ull) gm = (n_grp >= 64) ? ~0ull : ((1ull << n_grp) - 1ull);
+    if (gm & 1ull) cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+    gm &= ~1ull;
+    while (gm) {
+        const int g = __builtin_ctzll(gm);
+        gm &= gm - 1ull;
         cull_group<S>(otab[g * 64 + lane], otab + g * 64, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+    }
     return cnt;
 }
 
@@ -616,6 +672,8 @@ __device__ __forceinline__ float wave_min(float v) {
     v = fminf(v, xor_f32_1(v));
     return v;
 }
+
+__device__ __forceinline__ float wave_maxf(float v) { return -wave_min(-v); }
 
 // ---- gradients (adjoint of one rollout) ----
 

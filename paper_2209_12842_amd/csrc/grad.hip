@@ -124,8 +124,7 @@ __global__ void __launch_bounds__(256) k_grad_rollouts(StepConst c, GradArgs a) 
         us = a.u[(size_t)tn * K + k];
         vs = make_float2(a.V[2 * tn], a.V[2 * tn + 1]);
         const float tnd = tan_steer(uu.y);
-        float r = x.psi * 0.159154943091895335769f;
-        r = r - rintf(r);
+        const float r = x.psi * 0.159154943091895335769f;  // as in bicycle_step
         const float sn = __builtin_amdgcn_sinf(r), cs = __builtin_amdgcn_cosf(r);
         const float dt = c.dt, dv = dt * x.v;
         const float gua = dt * lam.w;                                                 // d v' / d a

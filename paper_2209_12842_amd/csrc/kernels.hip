@@ -231,7 +231,8 @@ hipError_t launch_serve(const StepConst& c, const StepBuffers& b, int block, siz
 int update_parts(int T) { return T >= 256 ? 1 : 256 / T; }
 
 size_t update_lds_bytes(int T, int G) {
-    const size_t slices = (size_t)update_parts(T) * 2 * T + 257 + 256;  // slice sums, non-zero weight list
+    // slice sums, the list of non-zero weights, the mean sequence
+    const size_t slices = (size_t)update_parts(T) * 2 * T + 257 + 256 + 2 * (size_t)T;
     const size_t merge = 2 * (size_t)G + 2 * (size_t)T;
     return 4 * (256 + (slices > merge ? slices : merge));
 }

@@ -32,6 +32,29 @@ __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs,
     return make_float4(0.0f, 0.0f, -__builtin_inff(), -__builtin_inff());
 }
 
+// The group boxes of the broad phase's group skip (kGroupPad): for each group
+// g of 64 table entries, the union of its discs' squares |x - cx|, |y - cy|
+// <= sqrt(q) widened by kGroupPad, as (x0, x1, y0, y1) in gbox[g]; entries
+// n_grp..63 get a box that meets nothing.  One whole wave computes them
+// (lane j takes entry 64 g + j, computed as obstacle_entry computes it),
+// before the barrier that precedes the rollouts.
+__device__ __forceinline__ void group_bounds(const float4* __restrict__ obs, int n_obs, int n_grp, float fx,
+                                             float fy, float4* gbox) {
+    const int lane = threadIdx.x & 63;
+    const float inf = __builtin_inff();
+    if (lane >= n_grp) gbox[lane] = make_float4(inf, -inf, inf, -inf);
+    for (int g = 0; g < n_grp; ++g) {
+        const int i = 64 * g + lane;
+        const bool valid = i < n_obs;
+        const float4 e = obstacle_entry(obs, n_obs, i, fx, fy);
+        const float cx = -0.5f * e.x, cy = -0.5f * e.y;  // exact: e.x = -2 cx
+        const float R = valid ? __builtin_amdgcn_sqrtf(e.w) : 0.0f;
+        const float x0 = wave_min(valid ? cx - R : inf), x1 = wave_maxf(valid ? cx + R : -inf);
+        const float y0 = wave_min(valid ? cy - R : inf), y1 = wave_maxf(valid ? cy + R : -inf);
+        if (lane == 0) gbox[g] = make_float4(x0 - kGroupPad, x1 + kGroupPad, y0 - kGroupPad, y1 + kGroupPad);
+    }
+}
+
 // LDS layout of k_rollout (dynamic shared memory, in this order):
 //   float2 ctl[spb * T]   (dt a, tan(delta) / wheelbase) of the WG's samples
 //   float  vals[spb * M]  risk costs of the WG's samples
@@ -39,8 +62,9 @@ __device__ __forceinline__ float4 obstacle_entry(const float4* __restrict__ obs,
 //   float  means[spb]     mean risk cost per sample (risk scaling)
 //   float4 otab[64 n_grp] the obstacle table, padded to groups of 64 entries
 //                         (16-byte aligned; n_grp = ceil(n_obs / 64))
+//   float4 gbox[64]       the groups' boxes for the group skip (group_bounds)
 // rollout_otab_offset gives the offset of otab in floats.  Every workgroup
-// writes otab from the raw obstacles before its rollouts.
+// writes otab and gbox from the raw obstacles before its rollouts.
 __host__ __device__ __forceinline__ int rollout_otab_offset(int spb, int T, int M) {
     return (2 * spb * T + 2 * spb * M + spb + 3) & ~3;
 }
@@ -145,7 +169,9 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     const int spb = c.spb, M = c.M, T = c.T;
     const int n_grp = rollout_n_grp(c.n_obs);
     float4* otab = reinterpret_cast<float4*>(reinterpret_cast<float*>(smem) + rollout_otab_offset(spb, T, M));
+    float4* gbox = otab + 64 * n_grp;
     for (int i = tid; i < n_grp * 64; i += blockDim.x) otab[i] = obstacle_entry(obs, c.n_obs, i, c.fx, c.fy);
+    if (n_grp > 1 && tid < 64) group_bounds(obs, c.n_obs, n_grp, c.fx, c.fy, gbox);
     int n_cand = 0;  // exact obstacle tests (state step, obstacle) of this wave (wave-uniform)
 
     if (item < c.n_nom_wg) {
@@ -208,7 +234,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
                     }
                 }
             }
-            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, n_grp, e0, px, py, n, n_cand);
+            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand);
         }
         float S = __fmaf_rn(c.c_obs, (float)cnt, acc);
         if (c.use_ctrl) S += ctrl;
@@ -302,7 +328,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
                     }
                 }
             }
-            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, n_grp, e0, px, py, n, n_cand);
+            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand);
         }
         if (active) {
             L = __fmaf_rn(c.c_obs, (float)cnt, acc);
@@ -369,23 +395,36 @@ __device__ __forceinline__ float seg_min_256(const float* v, float* red) {
 //     in debug mode, w_hat; in gradient mode J, every w_hat and the list of
 //     samples of non-zero weight instead, V unchanged.
 // LDS (dynamic, ush): w[256] | slice sums [parts][2T] | nzpos[257] |
-// nzlist[256], then for the merge v[256] | scale[G] | zb[G] | vp[2T]
-// (update_lds_bytes).
-template <int kB>
+// nzlist[256] | mean sequence [2T], then for the merge v[256] | scale[G] |
+// zb[G] | vp[2T] (update_lds_bytes).
+//
+// With kRegen (the update inside the rollout launch, where V is unchanged
+// until the merge) a chunk with at most kRegenMax samples of non-zero weight
+// draws their controls again from the same Philox counters and the same V
+// instead of reading the stored ones: sample_control is the function that
+// drew them, so the values are the same bits, and the sums see no load
+// latency (with the costs spread over many times lambda, as on the
+// receding-horizon workload, a chunk typically holds one such sample).
+constexpr int kRegenMax = 16;
+template <int kB, bool kRegen = false>
 __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int parts, const float* __restrict__ S,
                                              const float* __restrict__ cvar, const float2* __restrict__ u,
                                              float* __restrict__ S_tilde, float* __restrict__ part, float* ush,
-                                             float* red) {
+                                             float* red, const float* __restrict__ V = nullptr) {
     const int T = c.T, K = c.K;
     const int tid = threadIdx.x, nt = blockDim.x;
     float* wsh = ush;
     float* psh = wsh + 256;
     int* nzpos = reinterpret_cast<int*>(psh + (size_t)parts * 2 * T);  // 257
     int* nzlist = nzpos + 257;                                          // 256
+    float* vsh = reinterpret_cast<float*>(nzlist + 256);                // 2T
     const int k0 = b * 256;
     const int n = min(256, K - k0);
     const int stride = 2 + 2 * T;
     const int slice = (n + parts - 1) / parts;
+    if (kRegen) {  // staged now, read after the barrier below
+        for (int i = tid; i < 2 * T; i += nt) vsh[i] = V[i];
+    }
 
     // 1. modified costs, the chunk's minimum beta_b, its weights and their
     // sum Z_b, and the samples of non-zero weight, all by the first wave:
@@ -434,6 +473,7 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     __syncthreads();  // wsh, nzpos and nzlist published
 
     // 2. weighted control sums over slices of the chunk, in index order
+    const bool regen = kRegen && nzpos[256] <= kRegenMax;
     for (int idx = tid; idx < T * parts; idx += nt) {
         const int t = idx / parts;  // neighbouring lanes read the slices of one row
         const int pr = idx % parts;
@@ -442,6 +482,15 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
         float ax = 0.0f, ay = 0.0f;
         int q = ka < kb ? nzpos[ka] : 0;
         const int qb = ka < kb ? nzpos[kb] : 0;
+        if (regen) {
+            for (; q < qb; ++q) {
+                const int k = nzlist[q];
+                const float ww = wsh[k];
+                const float2 uu = sample_control(c, vsh, k0 + k, t);
+                ax = __fmaf_rn(ww, uu.x, ax);
+                ay = __fmaf_rn(ww, uu.y, ay);
+            }
+        }
         for (; q + kB <= qb; q += kB) {  // kB loads in flight, then the sums in order
             float2 uu[kB];
             float ww[kB];
@@ -845,7 +894,7 @@ __device__ __forceinline__ void fused_update(const StepConst& c, const FuseArgs&
     if (nf == 0) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int i = 0; i < nf; ++i) {
-        update_chunk<kFuseBatch>(c, fin_sh[i], f.parts, S, cvar, u, f.S_tilde, f.part, ush, red);
+        update_chunk<kFuseBatch, true>(c, fin_sh[i], f.parts, S, cvar, u, f.S_tilde, f.part, ush, red, V);
         if (f.G == 1)  // its own record, visible to the workgroup after update_chunk's barrier
             update_merge_single(c, f.part, f.S_tilde, V, f.u0, c.u0_seq ? f.u0_host : nullptr, f.w_hat, ush, red);
         else if (arrive_last(f.counter, (unsigned)f.G, flag_sh))

@@ -52,7 +52,7 @@ BAD = [
     dict(sigma_eps=(0.0, 0.1)), dict(sigma_eps=(-1.0, 0.1)), dict(sigma_w=(0.01, -0.01, 0.0, 0.0)),
     dict(alpha=0.0), dict(alpha=1.0), dict(alpha=1.5), dict(lam=0.0), dict(lam=float("inf")),
     dict(gamma=-0.1), dict(gamma=2.0), dict(eta=-0.1), dict(eta=1.1), dict(A=-1.0), dict(B=-1.0),
-    dict(C_u=float("nan")), dict(c_obs=float("inf")), dict(track=(0.0, 0.0, 0.0, 10.0, 3.0)),
+    dict(C_u=float("nan")), dict(c_obs=float("inf")), dict(c_v=-1.0), dict(track=(0.0, 0.0, 0.0, 10.0, 3.0)),
     dict(track=(0.0, 0.0, 15.0, 10.0, -1.0)), dict(noise_kind=3), dict(noise_kind=2, jump_prob=1.5),
     dict(noise_kind=2, jump_size=-0.1),
 ]

@@ -313,6 +313,17 @@ def test_one_launch_step_equals_split_update(name, kw):
     b.close()
 
 
+@pytest.mark.parametrize("turns", [0, 17, -160])
+def test_start_heading_far_from_zero(turns):
+    # the same start heading plus whole turns: beyond 100 rad the library
+    # reduces it modulo 2 pi before the rollouts (the hardware sine and cosine
+    # then see small arguments); the oracle takes it as given in FP64
+    p, obs, x0, V0 = _world("c1")
+    x0 = np.array(x0, dtype=np.float32)
+    x0[2] = np.float32(float(x0[2]) + 2.0 * np.pi * turns)
+    _run(p, obs, x0, V0, 1, tag="c1 heading %+d turns (%.4f rad)" % (turns, float(x0[2])))
+
+
 def test_shift_and_first_command():
     p, obs, x0, V0 = _world("c1", shift=True)
     g, o, rep = _run(p, obs, x0, V0, 0, shift=True, tag="c1 shift")
