@@ -115,22 +115,28 @@ TIMING_EVERY = 4
 CULL_STEPS = 6
 
 
-def executed_flops(p: dict, n_obs: int, candidates: float, block: int | None = None) -> float:
-    """FP32 FLOPs the rollout kernel executes in one launch (FMA = 2):
-    80 per disturbed state step for dynamics, noise and the smooth costs;
-    per disturbed lane 4 per state step for the extent of the broad-phase
-    box, and 17 per box (one per CULL_STEPS steps) and table slot (groups of
-    64) for the box test; 5 per lane for each exact test of a (state step,
-    candidate disc) pair (`candidates` counted on the device, per wave);
-    60 + 7 per padded obstacle (every obstacle tested) per nominal state
-    step."""
+def executed_flops(p: dict, n_obs: int, candidates: float, group_tests: float, block: int | None = None) -> float:
+    """FP32 FLOPs the rollout kernel executes in one launch (FMA = 2,
+    compares count one): 80 per disturbed state step and 60 per nominal state
+    step for dynamics, noise and the smooth costs; per lane (disturbed and
+    nominal) 4 per state step for the extent of the broad-phase box and, with
+    more than one table group, 4 per box (one per CULL_STEPS steps) for the
+    group-box compares; 17 per lane for each group test that ran
+    (`group_tests` counted on the device, per wave); 5 per lane for each
+    exact test of a (state step, candidate disc) pair (`candidates` counted
+    on the device, per wave)."""
     K, T, M = p["K"], p["T"], p["M"]
     n_grp = (n_obs + 63) // 64
-    n_tab = (n_obs + 7) // 8 * 8
     boxes = -(-T // CULL_STEPS)
-    lanes = 64 * disturbed_waves(p, block)
-    return (80.0 * K * M * T + (4.0 * T + 17.0 * n_grp * boxes) * lanes + 5.0 * 64 * candidates
-            + (60.0 + 7.0 * n_tab) * K * T)
+    spb = 1 if M >= 256 else 256 // M
+    if block is None:
+        block = (spb * M + 63) // 64 * 64
+    lanes = 64 * disturbed_waves(p, block) + (K + block - 1) // block * block
+    mask = 4.0 * boxes if n_grp > 1 else 0.0
+    if n_grp == 0:
+        return 80.0 * K * M * T + 60.0 * K * T
+    return (80.0 * K * M * T + 60.0 * K * T + (4.0 * T + mask) * lanes + 17.0 * 64 * group_tests
+            + 5.0 * 64 * candidates)
 
 
 def kernel_sources_sha256() -> str:
@@ -387,14 +393,14 @@ def run_plain(R, torch, workload: str, steps: int, warmup: int, serving: bool = 
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     roll_ms, upd_ms, n_timed = ctl.timing_read()
-    cand = ctl.timing_candidates() / max(n_timed, 1)
+    cand, gtests = (v / max(n_timed, 1) for v in ctl.timing_work())
     ctl.timing_enable(False)
     assert np.all(np.isfinite(V.cpu().numpy())) and np.all(np.isfinite(np.asarray(x)))
 
     steps_per_call = K * M * T
     value = steps_per_call * steps / elapsed
     roll_avg_s = roll_ms / max(n_timed, 1) * 1e-3
-    flops = executed_flops(p, n_obs, cand)
+    flops = executed_flops(p, n_obs, cand, gtests)
     achieved_tf = flops / roll_avg_s / 1e12
     brute_tf = model_flops(p, n_obs) / roll_avg_s / 1e12
     out = {
@@ -418,7 +424,7 @@ def run_plain(R, torch, workload: str, steps: int, warmup: int, serving: bool = 
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": measured_traffic(workload),
                      "kernel": "k_rollout", "executed_flops_per_launch": flops,
-                     "broad_phase_candidates_per_launch": cand,
+                     "broad_phase_candidates_per_launch": cand, "broad_phase_group_tests_per_launch": gtests,
                      "brute_force_equivalent_tflops": brute_tf,
                      "valu_issue": valu_issue(workload, roll_avg_s)},
     }
@@ -532,12 +538,13 @@ def run_batch(args, R, torch):
     for j in range(n_k):
         b.step(x, n_total + j, want_u0=False)
     roll_ms, upd_ms, n_timed = b.timing_read()
-    cand = b.timing_candidates() / max(n_timed, 1)
+    cand, gtests = (v / max(n_timed, 1) for v in b.timing_work())
     b.timing_enable(False)
     b.close()
 
     roll_avg_s = roll_ms / max(n_timed, 1) * 1e-3
-    flops = sum(executed_flops(w["params"], len(w["obstacles"]), 0.0, block=256) for w in ws) + 5.0 * 64 * cand
+    flops = (sum(executed_flops(w["params"], len(w["obstacles"]), 0.0, 0.0, block=256) for w in ws)
+             + 5.0 * 64 * cand + 17.0 * 64 * gtests)
     achieved_tf = flops / roll_avg_s / 1e12
     brute_tf = brute / roll_avg_s / 1e12
     value = work * args.steps / elapsed
@@ -561,6 +568,7 @@ def run_batch(args, R, torch):
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_TFLOPS, "traffic": None, "kernel": "k_batch_rollout",
                      "executed_flops_per_launch": flops, "broad_phase_candidates_per_launch": cand,
+                     "broad_phase_group_tests_per_launch": gtests,
                      "brute_force_equivalent_tflops": brute_tf},
     }
     print(json.dumps(out), flush=True)

@@ -272,8 +272,13 @@ mppi_status mppi_timing_read(mppi_handle *h, double *rollout_ms, double *update_
  * (wave, state step, obstacle) candidates that passed the broad phase and
  * were tested exactly, summed over the steps enqueued while timing was
  * enabled, since the last call.  Waits for `stream`, then clears the
- * counter. */
+ * counters (this one and the group-test counter of mppi_timing_work). */
 mppi_status mppi_timing_candidates(mppi_handle *h, void *stream, uint64_t *n_candidates);
+
+/* Both work counters of the obstacle test: the candidates as above, and the
+ * broad-phase group tests (a wave box against 64 table entries) that ran,
+ * per wave, after the group skip.  Waits for `stream`, then clears both. */
+mppi_status mppi_timing_work(mppi_handle *h, void *stream, uint64_t *n_candidates, uint64_t *n_group_tests);
 
 /* ---- Stage entry points (same device code as the fused step) ---- */
 
@@ -346,8 +351,9 @@ mppi_status mppi_batch_set_graph(mppi_batch *b, int enable);
  * records.  At most 4096 steps are kept. */
 mppi_status mppi_batch_timing_enable(mppi_batch *b, int enable);
 mppi_status mppi_batch_timing_read(mppi_batch *b, double *rollout_ms, double *update_ms, int32_t *n_steps);
-/* As mppi_timing_candidates, over the batch's timed steps. */
+/* As mppi_timing_candidates and mppi_timing_work, over the batch's timed steps. */
 mppi_status mppi_batch_timing_candidates(mppi_batch *b, void *stream, uint64_t *n_candidates);
+mppi_status mppi_batch_timing_work(mppi_batch *b, void *stream, uint64_t *n_candidates, uint64_t *n_group_tests);
 
 /* Device pointers of controller i's intermediate results (see mppi_debug_ptrs). */
 mppi_status mppi_batch_debug_view(const mppi_batch *b, int32_t i, mppi_debug_ptrs *out);

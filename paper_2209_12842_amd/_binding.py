@@ -118,6 +118,10 @@ def lib():
         L.mppi_timing_candidates.restype = I32
         L.mppi_batch_timing_candidates.argtypes = [V, V, P(U64)]
         L.mppi_batch_timing_candidates.restype = I32
+        L.mppi_timing_work.argtypes = [V, V, P(U64), P(U64)]
+        L.mppi_timing_work.restype = I32
+        L.mppi_batch_timing_work.argtypes = [V, V, P(U64), P(U64)]
+        L.mppi_batch_timing_work.restype = I32
         L.mppi_batch_destroy.argtypes = [V]
         L.mppi_batch_destroy.restype = ctypes.c_int
         _lib = L
@@ -283,6 +287,13 @@ class Controller:
         n = ctypes.c_uint64()
         check(lib().mppi_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(n)))
         return n.value
+
+    def timing_work(self) -> tuple:
+        """(exact obstacle tests, broad-phase group tests) over the steps timed since the last call."""
+        n, g = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().mppi_timing_work(self._h, ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(n),
+                                     ctypes.byref(g)))
+        return n.value, g.value
 
     def serve_start(self, V, idle_ms: int = 2000) -> None:
         """Starts a persistent serving launch (mppi_serve_start) that keeps V
@@ -465,6 +476,13 @@ class Batch:
         check(lib().mppi_batch_timing_candidates(self._h, ctypes.c_void_p(_stream_ptr(self.device)),
                                                  ctypes.byref(n)))
         return n.value
+
+    def timing_work(self) -> tuple:
+        """(exact obstacle tests, broad-phase group tests) over the batch's steps timed since the last call."""
+        n, g = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().mppi_batch_timing_work(self._h, ctypes.c_void_p(_stream_ptr(self.device)), ctypes.byref(n),
+                                           ctypes.byref(g)))
+        return n.value, g.value
 
     def debug(self, i: int) -> dict:
         torch = _torch()

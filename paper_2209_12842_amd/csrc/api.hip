@@ -138,7 +138,7 @@ Layout layout(const mppi_params* p) {
     l.part = o;    o += align_up(4 * (size_t)g.G * (2 + 2 * (size_t)p->T));
     l.u0 = o;      o += align_up(8);
     l.counter = o; o += align_up(4);
-    l.work = o;    o += align_up(8 * (size_t)ramppi::kWorkSlots);
+    l.work = o;    o += align_up(16 * (size_t)ramppi::kWorkSlots);
     l.chunk = o;   o += align_up(4 * (size_t)g.G);
     l.fuse = o;    o += align_up(sizeof(ramppi::FuseArgs));
     l.serve = o;   o += align_up(sizeof(ramppi::ServeReq) + sizeof(unsigned));  // request copy, go word
@@ -297,16 +297,22 @@ ramppi::StepBuffers step_buffers(const mppi_handle* h, float* V_dev) {
     return bufs;
 }
 
-// Sums and clears kWorkSlots device counters (waits for `s`).
-hipError_t read_work(unsigned long long* dev, hipStream_t s, uint64_t* out) {
-    unsigned long long host[ramppi::kWorkSlots];
+// Sums and clears the broad-phase work counters (kWorkSlots exact-test
+// slots, then kWorkSlots group-test slots; waits for `s`).  group_tests may
+// be NULL.
+hipError_t read_work(unsigned long long* dev, hipStream_t s, uint64_t* candidates, uint64_t* group_tests) {
+    unsigned long long host[2 * ramppi::kWorkSlots];
     hipError_t e = hipMemcpyAsync(host, dev, sizeof host, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipMemsetAsync(dev, 0, sizeof host, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    uint64_t sum = 0;
-    for (int i = 0; i < ramppi::kWorkSlots; ++i) sum += host[i];
-    *out = sum;
+    uint64_t c = 0, g = 0;
+    for (int i = 0; i < ramppi::kWorkSlots; ++i) {
+        c += host[i];
+        g += host[ramppi::kWorkSlots + i];
+    }
+    *candidates = c;
+    if (group_tests) *group_tests = g;
     return e;
 }
 
@@ -440,7 +446,7 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
     }
     e = hipMemcpyAsync(h->ws + l.obs, staged.data(), 16 * (size_t)p->n_obs, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.counter, 0, 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.work, 0, 8 * (size_t)ramppi::kWorkSlots, s);
+    if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.work, 0, 16 * (size_t)ramppi::kWorkSlots, s);
     if (e == hipSuccess) e = hipMemsetAsync(h->ws + l.chunk, 0, 4 * (size_t)h->g.G, s);
     if (e == hipSuccess && (p->flags & MPPI_F_GRAD)) e = hipMemsetAsync(h->ws + l.gcounter, 0, 4, s);
     // one launch per step when every workgroup of the step can be resident at
@@ -865,10 +871,18 @@ mppi_status mppi_timing_read(mppi_handle* h, double* rollout_ms, double* update_
     return MPPI_OK;
 }
 
+mppi_status mppi_timing_work(mppi_handle* h, void* stream, uint64_t* n_candidates, uint64_t* n_group_tests) {
+    if (!h || !n_candidates || !n_group_tests) return fail(MPPI_EINVAL, "NULL argument");
+    const hipError_t e = read_work(reinterpret_cast<unsigned long long*>(h->ws + h->l.work),
+                                   static_cast<hipStream_t>(stream), n_candidates, n_group_tests);
+    if (e != hipSuccess) return hip_fail(e, "broad-phase counters");
+    return MPPI_OK;
+}
+
 mppi_status mppi_timing_candidates(mppi_handle* h, void* stream, uint64_t* n_candidates) {
     if (!h || !n_candidates) return fail(MPPI_EINVAL, "NULL argument");
     const hipError_t e = read_work(reinterpret_cast<unsigned long long*>(h->ws + h->l.work),
-                                   static_cast<hipStream_t>(stream), n_candidates);
+                                   static_cast<hipStream_t>(stream), n_candidates, nullptr);
     if (e != hipSuccess) return hip_fail(e, "candidate counters");
     return MPPI_OK;
 }
@@ -993,7 +1007,7 @@ BatchLayout batch_layout(int32_t n, const mppi_params* p) {
     bl.items = o;   o += align_up(8 * (size_t)bl.n_items);
     bl.uitems = o;  o += align_up(8 * (size_t)bl.n_uitems);
     bl.queue = o;   o += align_up(8);
-    bl.work = o;    o += align_up(8 * (size_t)ramppi::kWorkSlots);
+    bl.work = o;    o += align_up(16 * (size_t)ramppi::kWorkSlots);
     bl.vbackup = o; o += vback;
     bl.ctl_base.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -1228,7 +1242,7 @@ mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* cons
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->ws + bl.uitems, uitems.data(), 8 * uitems.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.queue, 0, 8, s);
-    if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.work, 0, 8 * (size_t)ramppi::kWorkSlots, s);
+    if (e == hipSuccess) e = hipMemsetAsync(b->ws + bl.work, 0, 16 * (size_t)ramppi::kWorkSlots, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         batch_release(b);
@@ -1316,10 +1330,18 @@ mppi_status mppi_batch_timing_read(mppi_batch* b, double* rollout_ms, double* up
     return MPPI_OK;
 }
 
+mppi_status mppi_batch_timing_work(mppi_batch* b, void* stream, uint64_t* n_candidates, uint64_t* n_group_tests) {
+    if (!b || !n_candidates || !n_group_tests) return fail(MPPI_EINVAL, "NULL argument");
+    const hipError_t e = read_work(reinterpret_cast<unsigned long long*>(b->ws + b->bl.work),
+                                   static_cast<hipStream_t>(stream), n_candidates, n_group_tests);
+    if (e != hipSuccess) return hip_fail(e, "broad-phase counters");
+    return MPPI_OK;
+}
+
 mppi_status mppi_batch_timing_candidates(mppi_batch* b, void* stream, uint64_t* n_candidates) {
     if (!b || !n_candidates) return fail(MPPI_EINVAL, "NULL argument");
     const hipError_t e = read_work(reinterpret_cast<unsigned long long*>(b->ws + b->bl.work),
-                                   static_cast<hipStream_t>(stream), n_candidates);
+                                   static_cast<hipStream_t>(stream), n_candidates, nullptr);
     if (e != hipSuccess) return hip_fail(e, "candidate counters");
     return MPPI_OK;
 }

@@ -481,11 +481,12 @@ constexpr float kGroupPadP2 = 65536.0f;  // P^2 up to which kGroupPad covers the
 // px, py: the S points (entries past n repeat a valid point).  gbox: the 64
 // group boxes in LDS (see kGroupPad; boxes past n_grp meet nothing), read at
 // every call rather than held in registers through the rollout; n_grp == 1
-// tests the one group directly.
+// tests the one group directly.  n_gtest counts the group tests run
+// (wave-uniform).
 template <int S>
 __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ otab, const float4* gbox, int n_grp,
                                                     float4 e0, const float (&px)[S], const float (&py)[S], int n,
-                                                    int& n_cand) {
+                                                    int& n_cand, int& n_gtest) {
     const float xc = in_vgpr(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(px[0]))));
     const float yc = in_vgpr(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(py[0]))));
     float mx = fabsf(px[0] - xc), my = fabsf(py[0] - yc);
@@ -508,6 +509,7 @@ __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ o
     int cnt = 0;
     if (n_grp == 1) {
         cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+        ++n_gtest;
         return cnt;
     }
     const float4 gb = gbox[lane];  // 64 entries, empty past n_grp
@@ -517,12 +519,16 @@ __device__ __forceinline__ int obstacle_hits_culled(const float4* __restrict__ o
     // (P2 is the same in every lane: the ballot makes that known, so that
     // the mask stays in scalar registers)
     if (__builtin_amdgcn_ballot_w64(P2 > kGroupPadP2) != 0ull) gm = (n_grp >= 64) ? ~0ull : ((1ull << n_grp) - 1ull);
-    if (gm & 1ull) cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+    if (gm & 1ull) {
+        cull_group<S>(e0, otab, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+        ++n_gtest;
+    }
     gm &= ~1ull;
     while (gm) {
         const int g = __builtin_ctzll(gm);
         gm &= gm - 1ull;
         cull_group<S>(otab[g * 64 + lane], otab + g * 64, bx0, bx1, by0, by1, p2, px, py, rho, n, cnt, n_cand);
+        ++n_gtest;
     }
     return cnt;
 }

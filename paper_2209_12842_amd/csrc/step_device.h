@@ -81,8 +81,9 @@ struct BoolFalse {
 constexpr BoolTrue kTrue{};
 constexpr BoolFalse kFalse{};
 
-// Slots of the broad-phase candidate counters (wave w of item i adds to slot
-// (16 i + w) mod kWorkSlots, spreading the atomics).
+// Slots of the broad-phase work counters (wave w of item i adds to slot
+// (16 i + w) mod kWorkSlots, spreading the atomics): exact tests in
+// work[0..kWorkSlots), group tests in work[kWorkSlots..2 kWorkSlots).
 constexpr int kWorkSlots = 256;
 // Time steps whose points share one broad-phase box (obstacle_hits_culled):
 // a longer run divides the box and group tests over more steps but widens
@@ -172,7 +173,8 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     float4* gbox = otab + 64 * n_grp;
     for (int i = tid; i < n_grp * 64; i += blockDim.x) otab[i] = obstacle_entry(obs, c.n_obs, i, c.fx, c.fy);
     if (n_grp > 1 && tid < 64) group_bounds(obs, c.n_obs, n_grp, c.fx, c.fy, gbox);
-    int n_cand = 0;  // exact obstacle tests (state step, obstacle) of this wave (wave-uniform)
+    int n_cand = 0;   // exact obstacle tests (state step, obstacle) of this wave (wave-uniform)
+    int n_gtest = 0;  // broad-phase group tests of this wave (wave-uniform)
 
     if (item < c.n_nom_wg) {
         // ---- nominal rollouts: one lane per sample; lanes past K repeat
@@ -234,14 +236,17 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
                     }
                 }
             }
-            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand);
+            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand, n_gtest);
         }
         float S = __fmaf_rn(c.c_obs, (float)cnt, acc);
         if (c.use_ctrl) S += ctrl;
         if (c.use_term) S += terminal_cost(c, s);
         if (act) S_out[k] = S;
-        if (work && (tid & 63) == 0)
-            atomicAdd(&work[(item * 16 + (tid >> 6)) & (kWorkSlots - 1)], (unsigned long long)n_cand);
+        if (work && (tid & 63) == 0) {
+            const int slot = (item * 16 + (tid >> 6)) & (kWorkSlots - 1);
+            atomicAdd(&work[slot], (unsigned long long)n_cand);
+            atomicAdd(&work[kWorkSlots + slot], (unsigned long long)n_gtest);
+        }
         return;
     }
 
@@ -328,7 +333,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
                     }
                 }
             }
-            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand);
+            if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand, n_gtest);
         }
         if (active) {
             L = __fmaf_rn(c.c_obs, (float)cnt, acc);
@@ -346,8 +351,11 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         ranks[(size_t)k * M + id] = pos;
         if (pos < c.n_tail) tail_idx[(size_t)k * c.n_tail + pos] = id;
     }
-    if (work && (tid & 63) == 0)
-        atomicAdd(&work[(item * 16 + (tid >> 6)) & (kWorkSlots - 1)], (unsigned long long)n_cand);
+    if (work && (tid & 63) == 0) {
+        const int slot = (item * 16 + (tid >> 6)) & (kWorkSlots - 1);
+        atomicAdd(&work[slot], (unsigned long long)n_cand);
+        atomicAdd(&work[kWorkSlots + slot], (unsigned long long)n_gtest);
+    }
 }
 
 // Sum and minimum of 256 values held in LDS (v[0..255]) in a fixed order that

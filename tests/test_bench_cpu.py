@@ -14,13 +14,19 @@ def test_brute_force_model_matches_the_survey_counts():
 
 def test_executed_model_counts_waves_groups_and_candidates():
     p = dict(K=256, T=10, M=64)
-    # 256 samples of 64 draws: 4 samples per workgroup of 256 threads, 64 workgroups of 4 waves
+    # 256 samples of 64 draws: 4 samples per workgroup of 256 threads, 64
+    # workgroups of 4 waves, and one nominal workgroup of 256 lanes
     assert bench.disturbed_waves(p) == 256
-    base = bench.executed_flops(p, 10, 0.0)
+    base = bench.executed_flops(p, 10, 0.0, 0.0)
+    lanes = 64 * 256 + 256
+    assert base == 80.0 * 256 * 64 * 10 + 60.0 * 256 * 10 + 4.0 * 10 * lanes
+    assert bench.executed_flops(p, 10, 3.0, 0.0) - base == 5.0 * 64 * 3.0
+    assert bench.executed_flops(p, 10, 0.0, 2.0) - base == 17.0 * 64 * 2.0
+    # with more than one table group every box also runs the group-box compares
     boxes = -(-10 // bench.CULL_STEPS)
-    assert base == (80.0 * 256 * 64 * 10 + (4.0 * 10 + 17.0 * 1 * boxes) * 64 * 256
-                    + (60.0 + 7.0 * 16) * 256 * 10)
-    assert bench.executed_flops(p, 10, 3.0) - base == 5.0 * 64 * 3.0
+    assert bench.executed_flops(p, 100, 0.0, 0.0) - base == 4.0 * boxes * lanes
+    # no obstacles: no box at all
+    assert bench.executed_flops(p, 0, 0.0, 0.0) == 80.0 * 256 * 64 * 10 + 60.0 * 256 * 10
     # the batched path runs workgroups of 256 threads whatever M is
     q = dict(K=256, T=10, M=129)
     assert bench.disturbed_waves(q) == 256 * 3 and bench.disturbed_waves(q, block=256) == 256 * 4
