@@ -100,11 +100,12 @@ constexpr int kCullSteps = 6;
 // way the n_tail largest land in tail[0..n_tail-1] in that order and are
 // summed in it, so both give the same bits.  pos_out / id_out receive one
 // (position, draw index) pair of the sorted order per lane; together the
-// lanes of a sample cover every draw once.
+// lanes of a sample cover every draw once.  tid is the thread's index in the
+// workgroup (a caller may pass a copy the compiler cannot tie to values it
+// derived from the index earlier).
 __device__ __forceinline__ float cvar_epilogue(float* vals, float* tail, float* means, int spb, int M,
                                                int n_tail, int scale_risk, float B, int* pos_out = nullptr,
-                                               int* id_out = nullptr) {
-    const int tid = threadIdx.x;
+                                               int* id_out = nullptr, int tid = (int)threadIdx.x) {
     const int sl = tid / M;
     const int m = tid - sl * M;
     const bool own = sl < spb;
@@ -335,21 +336,30 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
             }
             if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand, n_gtest);
         }
-        if (active) {
-            L = __fmaf_rn(c.c_obs, (float)cnt, acc);
-            if (c.debug) L_out[(size_t)k * M + m] = L;
-        }
+        L = __fmaf_rn(c.c_obs, (float)cnt, acc);
     }
-    if (sl < spb) {
-        vals[tid] = L;
-        tail[tid] = __builtin_nanf("");
+    // The lane's sample and draw again, from copies of the thread index and
+    // of M that the compiler cannot tie to the ones above: the values derived
+    // before the rollout (the quotient, the divisor's reciprocal) then need
+    // no register through it (the rollout kernel runs at its register limit,
+    // and keeping them cost scratch-memory spills).
+    int tid_e = tid, M_e = M;
+    asm volatile("" : "+v"(tid_e), "+s"(M_e));
+    const int sl_e = tid_e / M_e;
+    const int m_e = tid_e - sl_e * M_e;
+    const int k_e = wg * spb + sl_e;
+    const bool active_e = (sl_e < spb) && (k_e < c.K);
+    if (active_e && c.debug) L_out[(size_t)k_e * M + m_e] = L;
+    if (sl_e < spb) {
+        vals[tid_e] = active_e ? L : 0.0f;
+        tail[tid_e] = __builtin_nanf("");
     }
-    int pos = M, id = m;
-    const float cv = cvar_epilogue(vals, tail, means, spb, M, c.n_tail, c.scale_risk, c.B, &pos, &id);
-    if (active && m == 0) cvar_out[k] = cv;
-    if (c.grad && active) {  // tail membership for the gradient
-        ranks[(size_t)k * M + id] = pos;
-        if (pos < c.n_tail) tail_idx[(size_t)k * c.n_tail + pos] = id;
+    int pos = M, id = m_e;
+    const float cv = cvar_epilogue(vals, tail, means, spb, M_e, c.n_tail, c.scale_risk, c.B, &pos, &id, tid_e);
+    if (active_e && m_e == 0) cvar_out[k_e] = cv;
+    if (c.grad && active_e) {  // tail membership for the gradient
+        ranks[(size_t)k_e * M + id] = pos;
+        if (pos < c.n_tail) tail_idx[(size_t)k_e * c.n_tail + pos] = id;
     }
     if (work && (tid & 63) == 0) {
         const int slot = (item * 16 + (tid >> 6)) & (kWorkSlots - 1);
