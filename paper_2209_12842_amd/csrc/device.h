@@ -248,32 +248,6 @@ __device__ __forceinline__ StepConst with_vector_constants_nominal(const StepCon
     return v;
 }
 
-// The disturbed successor F(x, u) + w (Eq. 6) of a state s that already
-// holds F(x, u), for the disturbance of Philox words r.  In the Gaussian form
-// each component's scale and its Box-Muller factor fold into the addition
-// (w_x = sqrt(Sigma_w,x) rad cos(2 pi u1) added by one fused multiply-add
-// onto x); the other forms add w as it is.  Every rollout that needs the
-// disturbed dynamics (the risk costs and the gradient's recomputation) uses
-// this, so all of them see the same states.
-// exp_word: 0x7F, the exponent word of uniform01 (in a vector register in
-// the hot loop).
-template <int kNoise>
-__device__ __forceinline__ State disturbed_successor(const StepConst& c, uint4 r, const State& s,
-                                                     uint32_t exp_word = 0x7Fu) {
-    if (kNoise == 0) {
-        const float u1 = uniform01(r.y, exp_word), u3 = uniform01(r.w, exp_word);
-        const float ra =
-            __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(r.x, exp_word)));
-        const float rb =
-            __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(r.z, exp_word)));
-        return State{__fmaf_rn(c.sw0 * ra, __builtin_amdgcn_cosf(u1), s.x),
-                     __fmaf_rn(c.sw1 * ra, __builtin_amdgcn_sinf(u1), s.y),
-                     __fmaf_rn(c.sw2 * rb, __builtin_amdgcn_cosf(u3), s.psi),
-                     __fmaf_rn(c.sw3 * rb, __builtin_amdgcn_sinf(u3), s.v)};
-    }
-    const float4 w = disturbance<kNoise>(c, r);
-    return State{s.x + w.x, s.y + w.y, s.psi + w.z, s.v + w.w};
-}
 
 template <int kNoise>
 __device__ __forceinline__ float4 disturbance(const StepConst& c, uint4 r) {
@@ -290,6 +264,64 @@ __device__ __forceinline__ float4 disturbance(const StepConst& c, uint4 r) {
         const float j = uniform01(r.x) < c.jump_prob ? c.jump_size : 0.0f;
         return make_float4(j * __builtin_amdgcn_cosf(u1), j * __builtin_amdgcn_sinf(u1), 0.0f, 0.0f);
     }
+}
+
+// The state-independent part of one disturbance: in the Gaussian form the
+// two Box-Muller radii and the uniforms of the two angles (ra, rb, u1, u3);
+// in the uniform form the four values 2u - 1; in the impulse form the jump
+// length (0 without a jump) and its angle's uniform.
+template <int kNoise>
+__device__ __forceinline__ float4 disturbance_draw(const StepConst& c, uint4 r, uint32_t exp_word) {
+    if (kNoise == 0) {
+        const float ra =
+            __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(r.x, exp_word)));
+        const float rb =
+            __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(uniform01(r.z, exp_word)));
+        return make_float4(ra, rb, uniform01(r.y, exp_word), uniform01(r.w, exp_word));
+    } else if (kNoise == 1) {
+        return make_float4(__fmaf_rn(2.0f, uniform01(r.x, exp_word), -1.0f),
+                           __fmaf_rn(2.0f, uniform01(r.y, exp_word), -1.0f),
+                           __fmaf_rn(2.0f, uniform01(r.z, exp_word), -1.0f),
+                           __fmaf_rn(2.0f, uniform01(r.w, exp_word), -1.0f));
+    } else {
+        const float j = uniform01(r.x, exp_word) < c.jump_prob ? c.jump_size : 0.0f;
+        return make_float4(j, uniform01(r.y, exp_word), 0.0f, 0.0f);
+    }
+}
+
+// The disturbed successor F(x, u) + w from a disturbance_draw, each
+// component's disturbance folded into its addition by one fused
+// multiply-add: sqrt(Sigma_w) rad cos(2 pi u) (Gaussian), h (2u - 1)
+// (uniform), jump cos(2 pi u) and jump sin(2 pi u) on x, y (impulse;
+// heading and speed unchanged).
+template <int kNoise>
+__device__ __forceinline__ State disturbed_successor_drawn(const StepConst& c, float4 d, const State& s) {
+    if (kNoise == 0)
+        return State{__fmaf_rn(c.sw0 * d.x, __builtin_amdgcn_cosf(d.z), s.x),
+                     __fmaf_rn(c.sw1 * d.x, __builtin_amdgcn_sinf(d.z), s.y),
+                     __fmaf_rn(c.sw2 * d.y, __builtin_amdgcn_cosf(d.w), s.psi),
+                     __fmaf_rn(c.sw3 * d.y, __builtin_amdgcn_sinf(d.w), s.v)};
+    if (kNoise == 1)
+        return State{__fmaf_rn(c.sw0, d.x, s.x), __fmaf_rn(c.sw1, d.y, s.y), __fmaf_rn(c.sw2, d.z, s.psi),
+                     __fmaf_rn(c.sw3, d.w, s.v)};
+    return State{__fmaf_rn(d.x, __builtin_amdgcn_cosf(d.y), s.x), __fmaf_rn(d.x, __builtin_amdgcn_sinf(d.y), s.y),
+                 s.psi, s.v};
+}
+
+// The disturbed successor F(x, u) + w (Eq. 6) of a state s that already
+// holds F(x, u), for the disturbance of Philox words r: disturbance_draw,
+// then disturbed_successor_drawn (each component's scale and disturbance
+// folded into its addition by one fused multiply-add).  Every rollout that
+// needs the disturbed dynamics (the risk costs and the gradient's
+// recomputation) goes through these two, so all of them see the same
+// states.  The fused multiply-adds are written out, so the bits do not
+// depend on which multiply-add pairs the compiler would contract.
+// exp_word: 0x7F, the exponent word of uniform01 (in a vector register in
+// the hot loop).
+template <int kNoise>
+__device__ __forceinline__ State disturbed_successor(const StepConst& c, uint4 r, const State& s,
+                                                     uint32_t exp_word = 0x7Fu) {
+    return disturbed_successor_drawn<kNoise>(c, disturbance_draw<kNoise>(c, r, exp_word), s);
 }
 
 // Headings beyond this magnitude (radians) are reduced modulo 2 pi before a

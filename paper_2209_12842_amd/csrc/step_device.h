@@ -276,7 +276,6 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     const int sl = tid / M;
     const int m = tid - sl * M;
     const int k = wg * spb + sl;
-    const bool active = (sl < spb) && (k < c.K);
     float L = 0.0f;
     {
         const StepConst cv = with_vector_constants(c);
