@@ -32,6 +32,11 @@ line on stdout:
   paper_shape  the paper's own sample counts (K = 1024, T = 30, M = 300,
                10 obstacles on the 0.6 m paper-preset oval): update rate in Hz
                beside the paper's
+  c5_batched   the batched-serving leg (--workload c5) in short: 64
+               controllers per step call, rate, latency, kernel times and the
+               64 sequential steps beside it
+  c4_gradient  the gradient leg (--grad) in short: dJ/dV evaluations per
+               second, cost against a plain step, equal-wall-time comparison
   paper        the paper's update rate with its hardware (context only)
   cpu_baseline the FP64 oracle on a bounded sample of the same workload,
                timed on this host's cores (all of them, and one thread on a
@@ -296,6 +301,8 @@ def main():
     ap.add_argument("--study", action="store_true")
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-legs", action="store_true",
+                    help="leave the batched (c5) and gradient (c4) legs out of the default line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy a MIB-sized device buffer 3 times (a plain copy kernel of "
                          "known size for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -309,11 +316,13 @@ def main():
     import paper_2209_12842_amd as R
 
     if args.grad:
-        return run_grad(args, R, torch)
+        print(json.dumps(run_grad(args, R, torch)), flush=True)
+        return
     if args.study:
         return run_study(args, R, torch)
     if args.workload == "c5":
-        return run_batch(args, R, torch)
+        print(json.dumps(run_batch(args, R, torch)), flush=True)
+        return
     headline = args.workload is None
     if headline:
         args.workload = "c3"
@@ -332,6 +341,18 @@ def main():
             "config": ps["config"]["workload"], "value": ps["value"], "ms_per_step": ps["ms_per_step"],
             "update_rate_hz": 1e3 / ps["ms_per_step"], "latency_ms": ps["latency_ms"],
             "paper": PAPER_RATE}
+        if not args.no_extra_legs:
+            # the batched-serving and gradient legs (their own lines with
+            # --workload c5 / --grad), summarised beside the headline
+            b5 = run_batch(argparse.Namespace(steps=30, warmup=5), R, torch)
+            out["c5_batched"] = {k: b5[k] for k in ("metric", "value", "unit", "ms_per_step", "latency_ms",
+                                                     "sequential", "speedup_vs_sequential", "kernel_ms")}
+            out["c5_batched"]["config"] = b5["config"]["workload"]
+            out["c5_batched"]["roofline_frac"] = b5["roofline"]["frac"]
+            g4 = run_grad(argparse.Namespace(steps=50, warmup=5, workload=None), R, torch)
+            out["c4_gradient"] = {k: g4[k] for k in ("metric", "value", "unit", "ms_per_step", "plain_step_ms",
+                                                      "gradient_over_step", "equal_wall_time")}
+            out["c4_gradient"]["config"] = g4["config"]["workload"]
     out["paper"] = PAPER_RATE
     if args.calibrate_copy > 0:
         dev = torch.device("cuda", 0)
@@ -571,7 +592,7 @@ def run_batch(args, R, torch):
                      "broad_phase_group_tests_per_launch": gtests,
                      "brute_force_equivalent_tflops": brute_tf},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_grad(args, R, torch):
@@ -655,8 +676,8 @@ def run_grad(args, R, torch):
                             "grad_rounds": n_grad, "grad_s": t_grad, "J_plain": score(Vp),
                             "J_grad_corrected": score(Vg)},
     }
-    print(json.dumps(out), flush=True)
     ctl.close()
+    return out
 
 
 def run_study(args, R, torch):
