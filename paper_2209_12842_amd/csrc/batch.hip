@@ -54,12 +54,20 @@ __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restric
         const BatchCtl& b = ctls[__builtin_amdgcn_readfirstlane(cw.x)];
         const int w = __builtin_amdgcn_readfirstlane(cw.y);
         const StepConst c = b.c;
+        // the controller's buffers, read from device memory: in the global
+        // address space (as_global)
+        const float4* obs = as_global(b.obs);
+        const float* V = as_global(b.V);
+        float2* u = as_global(b.u);
+        float* S = as_global(b.S);
+        float* cvar = as_global(b.cvar);
+        float* L = as_global(b.L);
         if (c.noise_kind == 1)
-            rollout_body<1>(c, b.obs, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
+            rollout_body<1>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
         else if (c.noise_kind == 2)
-            rollout_body<2>(c, b.obs, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
+            rollout_body<2>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
         else
-            rollout_body<0>(c, b.obs, b.V, b.u, b.S, b.cvar, b.L, w, bsmem, nullptr, nullptr, work);
+            rollout_body<0>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
         __syncthreads();  // LDS is reused by the next item
     }
     if (threadIdx.x == 0) {
@@ -79,8 +87,9 @@ __global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict
     const int2 cb = uitems[blockIdx.x];
     const BatchCtl& b = ctls[cb.x];
     const StepConst c = b.c;
-    update_body(c, cb.y, b.G, b.parts, b.S, b.cvar, b.u, b.S_tilde, b.part, b.counter, b.V, b.u0, b.u0_host,
-                b.w_hat, bush, red, &is_last);
+    update_body(c, cb.y, b.G, b.parts, as_global(b.S), as_global(b.cvar), as_global(b.u), as_global(b.S_tilde),
+                as_global(b.part), as_global(b.counter), as_global(b.V), as_global(b.u0), as_global(b.u0_host),
+                as_global(b.w_hat), bush, red, &is_last);
 }
 
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {

@@ -62,6 +62,19 @@ __device__ __forceinline__ uint32_t in_vgpr_u(uint32_t s) {
     return v;
 }
 
+// A pointer read from device memory (not a kernel argument) into device or
+// mapped host memory, in the global address space.  The compiler cannot tell
+// where such a pointer points and accesses it with flat instructions, which
+// also count against the LDS counter: every later wait for an LDS access
+// then waits for them too (after a device-scope acquire, a memory round
+// trip).  The integer round trip keeps the compiler from folding the
+// address-space cast away, so the accesses through the result compile to
+// global instructions.
+template <class T>
+__device__ __forceinline__ T* as_global(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 // The keys of the fourth to the tenth round in vector registers (the rounds
 // before them XOR words that are still the same in every lane, on the
 // scalar unit).
@@ -202,6 +215,8 @@ struct StepConst {
     uint32_t key0, key1, step_idx, flags;
     int32_t use_bdry, use_term, use_ctrl, scale_risk, debug;
     int32_t grad;        // record tail ranks for the gradient of the free energy
+    int32_t store_u;     // store the sampled controls (the two-launch update reads them;
+                         // the one-launch update draws them again)
     uint32_t u0_seq;     // nonzero: after the first command, store this value to
                          // the word after it in mapped host memory (the host waits on it)
 };

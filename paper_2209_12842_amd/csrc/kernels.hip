@@ -35,7 +35,7 @@ __device__ __forceinline__ void rollout_launch_body(const StepConst& c, const fl
         __shared__ float red[16];
         __shared__ int flag_sh;
         __shared__ int fin_sh[8];
-        const FuseArgs f = *fa;
+        const FuseArgs f = global_view(*fa);
         // V is read by the rollouts and rewritten by the merge, which runs
         // only after every rollout of the step has finished
         fused_update(c, f, blockIdx.x, S_out, cvar_out, u_out, const_cast<float*>(V),
@@ -77,8 +77,9 @@ template <int kNoise>
 __global__ void __launch_bounds__(1024) k_serve(StepConst c0, const float4* __restrict__ obs, float* V,
                                                 float2* __restrict__ u_out, float* __restrict__ S_out,
                                                 float* __restrict__ cvar_out, float* __restrict__ L_out,
-                                                const FuseArgs* __restrict__ fa, ServeArgs sa) {
+                                                const FuseArgs* __restrict__ fa, ServeArgs sa_arg) {
     extern __shared__ float2 smem[];
+    const ServeArgs sa = global_view(sa_arg);
     __shared__ float red[16];
     __shared__ int flag_sh;
     __shared__ int fin_sh[8];
@@ -108,7 +109,7 @@ __global__ void __launch_bounds__(1024) k_serve(StepConst c0, const float4* __re
         c.step_idx = r->step_idx;
         c.u0_seq = seq;
         rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem);
-        const FuseArgs f = *fa;
+        const FuseArgs f = global_view(*fa);
         fused_update(c, f, blockIdx.x, S_out, cvar_out, u_out, V, reinterpret_cast<float*>(smem), red, &flag_sh,
                      fin_sh);
         __syncthreads();  // LDS and leave_sh are reused by the next request

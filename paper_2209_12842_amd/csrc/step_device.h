@@ -188,6 +188,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         __syncthreads();  // otab and V staged
         const int k = item * blockDim.x + tid;
         const bool act = k < c.K;
+        const bool store = act && c.store_u;
         const int kc = act ? k : c.K - 1;
         const float4 e0 = n_grp > 0 ? otab[tid & 63] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         State s{0.0f, 0.0f, c.psi0, c.v0};
@@ -201,7 +202,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         // when asked, so that the step holds no branch), then x_{t+1}
         auto step = [&](auto bdry, int t, float& px, float& py) {
             const float2 u = sample_control(cn, vsh, kc, t, vk, exp_word);
-            if (act) u_out[(size_t)t * c.K + k] = u;
+            if (store) u_out[(size_t)t * c.K + k] = u;
             acc = smooth_cost_acc<decltype(bdry)::value>(cn, s, acc);
             px = s.x;
             py = s.y;
@@ -416,13 +417,15 @@ __device__ __forceinline__ float seg_min_256(const float* v, float* red) {
 // zb[G] | vp[2T] (update_lds_bytes).
 //
 // With kRegen (the update inside the rollout launch, where V is unchanged
-// until the merge) a chunk with at most kRegenMax samples of non-zero weight
-// draws their controls again from the same Philox counters and the same V
-// instead of reading the stored ones: sample_control is the function that
-// drew them, so the values are the same bits, and the sums see no load
-// latency (with the costs spread over many times lambda, as on the
-// receding-horizon workload, a chunk typically holds one such sample).
-constexpr int kRegenMax = 16;
+// until the merge) the chunk draws the controls of its samples of non-zero
+// weight again from the same Philox counters and the same V instead of
+// reading stored ones: sample_control is the function that drew them, so the
+// values are the same bits.  Stored controls would have been written by
+// workgroups on other XCDs, and each round of loads waits about 1.4 us for
+// memory after the device-scope acquire, while a redrawn control costs a few
+// tens of instructions; so the one-launch step stores no controls (except in
+// debug mode, for the debug view), and even a chunk whose every weight is
+// non-zero is summed sooner than by loading.
 template <int kB, bool kRegen = false>
 __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int parts, const float* __restrict__ S,
                                              const float* __restrict__ cvar, const float2* __restrict__ u,
@@ -439,9 +442,11 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     const int n = min(256, K - k0);
     const int stride = 2 + 2 * T;
     const int slice = (n + parts - 1) / parts;
-    if (kRegen) {  // staged now, read after the barrier below
-        for (int i = tid; i < 2 * T; i += nt) vsh[i] = V[i];
-    }
+    // V (for the redrawn controls) is staged into LDS after the first step
+    // below, but the thread's first value is loaded now, so that its load and
+    // the first wave's loads of S and CVaR wait on memory together
+    const bool has_v = kRegen && tid < 2 * T;
+    const float v_first = has_v ? V[tid] : 0.0f;
 
     // 1. modified costs, the chunk's minimum beta_b, its weights and their
     // sum Z_b, and the samples of non-zero weight, all by the first wave:
@@ -456,15 +461,25 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
     // give the bits of the full sums.
     float beta_b = 0.0f, Z_b = 0.0f;
     if (tid < 64) {
+        // the eight loads first (a lane past the chunk's end reads its last
+        // sample and drops it), so that they wait on memory once, not once
+        // per segment
+        float cvl[4], sl[4];
+#pragma unroll
+        for (int sg = 0; sg < 4; ++sg) {
+            const int i = min(64 * sg + tid, n - 1);
+            cvl[sg] = cvar[k0 + i];
+            sl[sg] = S[k0 + i];
+        }
         float w[4];
 #pragma unroll
         for (int sg = 0; sg < 4; ++sg) {
             const int i = 64 * sg + tid;
             float st = __builtin_inff();
             if (i < n) {
-                const float cv = cvar[k0 + i];
+                const float cv = cvl[sg];
                 const float jc = (cv > c.C_u) ? c.A * cv : 0.0f;  // Eq. 14-15
-                st = S[k0 + i] + jc;                               // Eq. 16
+                st = sl[sg] + jc;                                  // Eq. 16
                 S_tilde[k0 + i] = st;
             }
             w[sg] = st;
@@ -487,19 +502,21 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
         }
         if (tid == 0) nzpos[256] = off;
     }
-    __syncthreads();  // wsh, nzpos and nzlist published
+    if (kRegen) {
+        if (has_v) vsh[tid] = v_first;
+        for (int i = tid + nt; i < 2 * T; i += nt) vsh[i] = V[i];
+    }
+    __syncthreads();  // wsh, nzpos, nzlist and V published
 
     // 2. weighted control sums over slices of the chunk, in index order
-    const bool regen = kRegen && nzpos[256] <= kRegenMax;
     for (int idx = tid; idx < T * parts; idx += nt) {
         const int t = idx / parts;  // neighbouring lanes read the slices of one row
         const int pr = idx % parts;
         const int ka = pr * slice, kb = min(n, ka + slice);
-        const float2* ut = u + (size_t)t * K + k0;
         float ax = 0.0f, ay = 0.0f;
         int q = ka < kb ? nzpos[ka] : 0;
         const int qb = ka < kb ? nzpos[kb] : 0;
-        if (regen) {
+        if constexpr (kRegen) {
             for (; q < qb; ++q) {
                 const int k = nzlist[q];
                 const float ww = wsh[k];
@@ -507,37 +524,39 @@ __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int part
                 ax = __fmaf_rn(ww, uu.x, ax);
                 ay = __fmaf_rn(ww, uu.y, ay);
             }
-        }
-        for (; q + kB <= qb; q += kB) {  // kB loads in flight, then the sums in order
-            float2 uu[kB];
-            float ww[kB];
+        } else {
+            const float2* ut = u + (size_t)t * K + k0;
+            for (; q + kB <= qb; q += kB) {  // kB loads in flight, then the sums in order
+                float2 uu[kB];
+                float ww[kB];
 #pragma unroll
-            for (int i = 0; i < kB; ++i) {
-                const int k = nzlist[q + i];
-                ww[i] = wsh[k];
-                uu[i] = ut[k];
-            }
+                for (int i = 0; i < kB; ++i) {
+                    const int k = nzlist[q + i];
+                    ww[i] = wsh[k];
+                    uu[i] = ut[k];
+                }
 #pragma unroll
-            for (int i = 0; i < kB; ++i) {
-                ax = __fmaf_rn(ww[i], uu[i].x, ax);
-                ay = __fmaf_rn(ww[i], uu[i].y, ay);
-            }
-        }
-        if (q < qb) {  // the rest in one more round
-            float2 uu[kB];
-            float ww[kB];
-#pragma unroll
-            for (int i = 0; i < kB; ++i) {
-                const bool in = q + i < qb;
-                const int k = in ? nzlist[q + i] : 0;
-                ww[i] = in ? wsh[k] : 0.0f;
-                uu[i] = in ? ut[k] : make_float2(0.0f, 0.0f);
-            }
-#pragma unroll
-            for (int i = 0; i < kB; ++i) {
-                if (q + i < qb) {
+                for (int i = 0; i < kB; ++i) {
                     ax = __fmaf_rn(ww[i], uu[i].x, ax);
                     ay = __fmaf_rn(ww[i], uu[i].y, ay);
+                }
+            }
+            if (q < qb) {  // the rest in one more round
+                float2 uu[kB];
+                float ww[kB];
+#pragma unroll
+                for (int i = 0; i < kB; ++i) {
+                    const bool in = q + i < qb;
+                    const int k = in ? nzlist[q + i] : 0;
+                    ww[i] = in ? wsh[k] : 0.0f;
+                    uu[i] = in ? ut[k] : make_float2(0.0f, 0.0f);
+                }
+#pragma unroll
+                for (int i = 0; i < kB; ++i) {
+                    if (q + i < qb) {
+                        ax = __fmaf_rn(ww[i], uu[i].x, ax);
+                        ay = __fmaf_rn(ww[i], uu[i].y, ay);
+                    }
                 }
             }
         }
@@ -791,6 +810,20 @@ struct FuseArgs {
     int G, parts;
 };
 
+// FuseArgs as read from device memory, its pointers in the global address
+// space (as_global).
+__device__ __forceinline__ FuseArgs global_view(const FuseArgs& f) {
+    FuseArgs g = f;
+    g.chunk_ctr = as_global(f.chunk_ctr);
+    g.counter = as_global(f.counter);
+    g.S_tilde = as_global(f.S_tilde);
+    g.part = as_global(f.part);
+    g.u0 = as_global(f.u0);
+    g.u0_host = as_global(f.u0_host);
+    g.w_hat = as_global(f.w_hat);
+    return g;
+}
+
 // ---- persistent serving: one resident launch runs step after step ----
 
 // One served step's request: the per-step constants the host derives from
@@ -812,6 +845,14 @@ struct ServeArgs {
     unsigned* go;              // request number being served, or kServeExit
     uint64_t idle_ticks;       // longest wait for a request (s_memrealtime ticks, 100 MHz)
 };
+
+__device__ __forceinline__ ServeArgs global_view(const ServeArgs& a) {
+    ServeArgs g = a;
+    g.req_host = as_global(a.req_host);
+    g.req_dev = as_global(a.req_dev);
+    g.go = as_global(a.go);
+    return g;
+}
 
 constexpr unsigned kServeExit = 0xFFFFFFFFu;
 
