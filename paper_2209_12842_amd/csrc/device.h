@@ -194,7 +194,7 @@ __device__ __forceinline__ float4 normals4(uint4 r) {
 struct StepConst {
     int32_t K, T, M, n_obs;
     int32_t spb;         // samples per disturbed workgroup
-    int32_t n_nom_wg;    // nominal workgroups at the front of the grid
+    int32_t n_nom_wg;    // nominal workgroups: items 0 .. n_nom_wg - 1 (rollout_item orders the grid)
     int32_t n_warm;      // samples k < n_warm keep the mean sequence
     int32_t n_tail;      // M - ceil(alpha M) + 1
     float dt, inv_wheelbase;

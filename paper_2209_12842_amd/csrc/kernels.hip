@@ -22,6 +22,22 @@
 
 namespace ramppi {
 
+// Workgroup order of the two-launch rollout kernel: the disturbed workgroups
+// first, the nominal ones last.  Its grids can be a little larger than what
+// the device holds at once (the paper's K = 1024, M = 300 step: 1024
+// disturbed workgroups of five waves fill the 1024 places of four per
+// compute unit, and four nominal ones remain); the workgroups that wait for
+// a free place are then the nominal ones, which take a fraction of a
+// disturbed workgroup's time (launch 72 -> 67 us; the large step is
+// unchanged).  The one-launch kernel keeps the nominal workgroups first:
+// they then start on compute units of their own choosing rather than as
+// the third workgroup of a unit (c2 about 1 us shorter that way).
+__device__ __forceinline__ int rollout_item(const StepConst& c) {
+    const int n_dist = (int)gridDim.x - c.n_nom_wg;
+    const int b = (int)blockIdx.x;
+    return b < n_dist ? c.n_nom_wg + b : b - n_dist;
+}
+
 template <int kNoise, bool kFuse>
 __device__ __forceinline__ void rollout_launch_body(const StepConst& c, const float4* __restrict__ obs,
                                                     const float* __restrict__ V, float2* __restrict__ u_out,
@@ -30,7 +46,8 @@ __device__ __forceinline__ void rollout_launch_body(const StepConst& c, const fl
                                                     int* __restrict__ tail_idx, unsigned long long* __restrict__ work,
                                                     const FuseArgs* __restrict__ fa) {
     extern __shared__ float2 smem[];
-    rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, blockIdx.x, smem, ranks, tail_idx, work);
+    const int item = kFuse ? (int)blockIdx.x : rollout_item(c);
+    rollout_body<kNoise>(c, obs, V, u_out, S_out, cvar_out, L_out, item, smem, ranks, tail_idx, work);
     if constexpr (kFuse) {
         __shared__ float red[16];
         __shared__ int flag_sh;
