@@ -968,6 +968,7 @@ struct BatchLayout {
     std::vector<size_t> ctl_base;
     size_t total;
     int n_items, n_uitems;
+    int noise_kind;  // the disturbance form of every controller, or -1 when they differ
     size_t lds_rollout, lds_update;
 };
 
@@ -996,8 +997,10 @@ BatchLayout batch_layout(int32_t n, const mppi_params* p) {
     bl.n_uitems = 0;
     bl.lds_rollout = 0;
     bl.lds_update = 0;
+    bl.noise_kind = (int)p[0].noise_kind;
     size_t vback = 0;
     for (int i = 0; i < n; ++i) {
+        if ((int)p[i].noise_kind != bl.noise_kind) bl.noise_kind = -1;
         const Geometry g = batch_geometry(&p[i]);
         bl.n_items += g.n_nom_wg + n_dist_wg(&p[i], g);
         bl.n_uitems += g.G;
@@ -1059,6 +1062,7 @@ ramppi::BatchLaunch batch_launch_args(const mppi_batch* b) {
     L.n_items = b->bl.n_items;
     L.n_uitems = b->bl.n_uitems;
     L.grid_rollout = b->wg_per_cu * b->num_cu;
+    L.noise_kind = b->bl.noise_kind;
     L.lds_rollout = b->bl.lds_rollout;
     L.lds_update = b->bl.lds_update;
     return L;
@@ -1168,7 +1172,7 @@ mppi_status mppi_batch_create(int32_t n, const mppi_params* p, const float* cons
     b->timing = false;
     b->n_timed = 0;
     hipError_t e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = ramppi::batch_rollout_occupancy(&b->wg_max, bl.lds_rollout);
+    if (e == hipSuccess) e = ramppi::batch_rollout_occupancy(&b->wg_max, bl.lds_rollout, bl.noise_kind);
     if (e == hipSuccess)
         e = hipHostMalloc(reinterpret_cast<void**>(&b->in_host), sizeof(ramppi::BatchInput) * (size_t)n,
                           hipHostMallocMapped | hipHostMallocCoherent);

@@ -39,9 +39,11 @@ __global__ void __launch_bounds__(64) k_batch_prep(BatchCtl* __restrict__ ctls, 
     if (i < n_ctl) set_dynamic(ctls[i].c, ctls[i], inputs[i]);
 }
 
-__global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restrict__ ctls,
-                                                       const int2* __restrict__ items, int n_items,
-                                                       unsigned* queue, unsigned long long* __restrict__ work) {
+// The loop of the persistent rollout kernel: kNoise >= 0 is the one
+// disturbance form of every controller of the batch; -1 picks it per item.
+template <int kNoise>
+__device__ __forceinline__ void batch_rollout_loop(const BatchCtl* __restrict__ ctls, const int2* __restrict__ items,
+                                                   int n_items, unsigned* queue, unsigned long long* __restrict__ work) {
     extern __shared__ float2 bsmem[];
     __shared__ int item_sh;
     for (;;) {
@@ -62,12 +64,16 @@ __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restric
         float* S = as_global(b.S);
         float* cvar = as_global(b.cvar);
         float* L = as_global(b.L);
-        if (c.noise_kind == 1)
-            rollout_body<1>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
-        else if (c.noise_kind == 2)
-            rollout_body<2>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
-        else
-            rollout_body<0>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
+        if constexpr (kNoise >= 0) {
+            rollout_body<kNoise>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
+        } else {
+            if (c.noise_kind == 1)
+                rollout_body<1>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
+            else if (c.noise_kind == 2)
+                rollout_body<2>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
+            else
+                rollout_body<0>(c, obs, V, u, S, cvar, L, w, bsmem, nullptr, nullptr, work);
+        }
         __syncthreads();  // LDS is reused by the next item
     }
     if (threadIdx.x == 0) {
@@ -77,6 +83,24 @@ __global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restric
             __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
+}
+
+// Controllers of several disturbance forms.
+__global__ void __launch_bounds__(256) k_batch_rollout(const BatchCtl* __restrict__ ctls,
+                                                       const int2* __restrict__ items, int n_items,
+                                                       unsigned* queue, unsigned long long* __restrict__ work) {
+    batch_rollout_loop<-1>(ctls, items, n_items, queue, work);
+}
+
+// One disturbance form for the whole batch: compiled, like the two-launch
+// rollout kernel, for five waves per SIMD (the kernel for several forms
+// needs the registers of the largest and holds four; on the 64-controller
+// batch the rollout launch 3.62 -> 3.57 ms).
+template <int kNoise>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+    k_batch_rollout_one(const BatchCtl* __restrict__ ctls, const int2* __restrict__ items, int n_items,
+                        unsigned* queue, unsigned long long* __restrict__ work) {
+    batch_rollout_loop<kNoise>(ctls, items, n_items, queue, work);
 }
 
 __global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict__ ctls,
@@ -95,14 +119,31 @@ __global__ void __launch_bounds__(256) k_batch_update(const BatchCtl* __restrict
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid) {
     hipLaunchKernelGGL(k_batch_prep, dim3((L.n_ctl + 63) / 64), dim3(64), 0, stream, L.ctls, L.inputs, L.n_ctl);
     if (ev_start) (void)hipEventRecord(ev_start, stream);
-    hipLaunchKernelGGL(k_batch_rollout, dim3(L.grid_rollout), dim3(256), L.lds_rollout, stream, L.ctls, L.items,
-                       L.n_items, L.queue, L.work);
+    const dim3 grid(L.grid_rollout);
+    if (L.noise_kind == 0)
+        hipLaunchKernelGGL(k_batch_rollout_one<0>, grid, dim3(256), L.lds_rollout, stream, L.ctls, L.items, L.n_items,
+                           L.queue, L.work);
+    else if (L.noise_kind == 1)
+        hipLaunchKernelGGL(k_batch_rollout_one<1>, grid, dim3(256), L.lds_rollout, stream, L.ctls, L.items, L.n_items,
+                           L.queue, L.work);
+    else if (L.noise_kind == 2)
+        hipLaunchKernelGGL(k_batch_rollout_one<2>, grid, dim3(256), L.lds_rollout, stream, L.ctls, L.items, L.n_items,
+                           L.queue, L.work);
+    else
+        hipLaunchKernelGGL(k_batch_rollout, grid, dim3(256), L.lds_rollout, stream, L.ctls, L.items, L.n_items,
+                           L.queue, L.work);
     if (ev_mid) (void)hipEventRecord(ev_mid, stream);
     hipLaunchKernelGGL(k_batch_update, dim3(L.n_uitems), dim3(256), L.lds_update, stream, L.ctls, L.uitems);
     return hipGetLastError();
 }
 
-hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout) {
+hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout, int noise_kind) {
+    if (noise_kind == 0)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_batch_rollout_one<0>, 256, lds_rollout);
+    if (noise_kind == 1)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_batch_rollout_one<1>, 256, lds_rollout);
+    if (noise_kind == 2)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_batch_rollout_one<2>, 256, lds_rollout);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, k_batch_rollout, 256, lds_rollout);
 }
 

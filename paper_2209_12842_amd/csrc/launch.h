@@ -64,12 +64,13 @@ struct BatchLaunch {
     unsigned* queue;           // 2 counters, zero between launches
     unsigned long long* work;  // kWorkSlots broad-phase candidate counters, or null
     int n_ctl, n_items, n_uitems, grid_rollout;
+    int noise_kind;            // the disturbance form of every controller, or -1 when they differ
     size_t lds_rollout, lds_update;
 };
 
 hipError_t launch_batch(const BatchLaunch& L, hipStream_t stream, hipEvent_t ev_start = nullptr,
                         hipEvent_t ev_mid = nullptr);
-hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout);
+hipError_t batch_rollout_occupancy(int* wg_per_cu, size_t lds_rollout, int noise_kind);
 
 // Buffers of the gradient of the free energy (see grad.hip).
 struct GradArgs {

@@ -95,6 +95,31 @@ def test_batch_equals_single_controller_steps(graph):
     b.close()
 
 
+@pytest.mark.parametrize("kind", [1, 2])
+def test_single_form_batch_equals_single_controller_steps(kind):
+    # every controller with the same disturbance form: the batch runs the
+    # rollout kernel compiled for that form alone (the Gaussian form is the
+    # 64-controller batch's)
+    ws = W.make_batch(4, seed=20 + kind, k_range=(256, 1024), t_range=(8, 30), m_range=(7, 64), obs_range=(0, 40))
+    for w in ws:
+        w["params"].update(noise_kind=kind)
+        if kind == 2:
+            w["params"].update(jump_prob=0.05, jump_size=0.45)
+        w["V0"] = W.random_V(w["params"]["T"], 4, scale=(1.0, 0.2))
+    n = len(ws)
+    b = R.Batch([w["params"] for w in ws], [w["obstacles"] for w in ws], debug=True, V0=[w["V0"] for w in ws])
+    x0s = np.stack([w["x0"] for w in ws])
+    idx = np.arange(n, dtype=np.uint32) + 9
+    _log("single-form batch, noise kind %d" % kind)
+    u0 = b.step(x0s, idx)
+    torch.cuda.synchronize()
+    ref = _plain(ws, x0s, [w["V0"] for w in ws], idx)
+    for i in range(n):
+        _same(_batch_state(b, i), ref[i], i)
+        assert np.array_equal(u0[i], ref[i]["u0h"])
+    b.close()
+
+
 def test_batch_autotune_keeps_results_and_state():
     ws = _mixed_worlds()
     n = len(ws)
