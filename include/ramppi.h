@@ -109,8 +109,8 @@ typedef struct {
 
 /* Device pointers into the workspace, valid while the handle lives.
  *   u        T x K x 2 sampled controls, time-major: u[(t*K + k)*2 + c];
- *            written with MPPI_F_DEBUG, or when the step runs as two launches
- *            (the one-launch update draws the controls it needs again).
+ *            written with MPPI_F_DEBUG and by mppi_grad (otherwise the update
+ *            draws the controls it needs again and none are stored).
  *   S        K nominal costs (Eq. 3).
  *   L        K x M risk costs (Eq. 9), row-major; written with MPPI_F_DEBUG.
  *   cvar     K CVaR values (Eq. 12, on the scaled costs of Eq. 18).

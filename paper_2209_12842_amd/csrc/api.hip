@@ -237,7 +237,7 @@ void fill_static(ramppi::StepConst* cp, const mppi_params& p, const Geometry& g,
     c.key1 = (uint32_t)(p.seed >> 32);
     c.flags = p.flags;
     c.debug = (p.flags & MPPI_F_DEBUG) != 0;
-    c.store_u = 1;
+    c.store_u = c.debug;  // the update draws the controls it needs again
 }
 
 // Per-launch constants that depend on the measured state and the call index
@@ -509,7 +509,6 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     ramppi::StepConst c;
     fill_static(&c, p, g, h->n_tail, h->n_warm);
     fill_dynamic(&c, p, x0, step_idx);
-    if (h->fuse && !c.debug) c.store_u = 0;  // the one-launch update draws the controls it needs again
 
     ramppi::StepBuffers bufs = step_buffers(h, V_dev);
     bufs.u0_host = u0_host ? h->u0_pinned_dev : nullptr;
@@ -692,7 +691,6 @@ mppi_status mppi_serve_start(mppi_handle* h, float* V_dev, uint32_t idle_ms, voi
     const float x0[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // the per-step fields come with each request
     fill_static(&c, p, g, h->n_tail, h->n_warm);
     fill_dynamic(&c, p, x0, 0);
-    if (!c.debug) c.store_u = 0;  // a served step is a one-launch step
     ramppi::StepBuffers bufs = step_buffers(h, V_dev);
     // workspace: request copy | go word
     char* sv = h->ws + h->l.serve;
@@ -796,6 +794,7 @@ mppi_status mppi_grad(mppi_handle* h, const float x0[4], const float* V_dev, uin
     fill_dynamic(&c, p, x0, step_idx);
     c.grad = 1;
     c.debug = 0;
+    c.store_u = 1;  // the gradient's recomputed rollouts read the controls
 
     ramppi::StepBuffers bufs = step_buffers(h, const_cast<float*>(V_dev));
     bufs.Vout = nullptr;

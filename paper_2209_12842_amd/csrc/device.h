@@ -215,8 +215,8 @@ struct StepConst {
     uint32_t key0, key1, step_idx, flags;
     int32_t use_bdry, use_term, use_ctrl, scale_risk, debug;
     int32_t grad;        // record tail ranks for the gradient of the free energy
-    int32_t store_u;     // store the sampled controls (the two-launch update reads them;
-                         // the one-launch update draws them again)
+    int32_t store_u;     // store the sampled controls (debug view, gradient); without them
+                         // the update draws the controls it needs again
     uint32_t u0_seq;     // nonzero: after the first command, store this value to
                          // the word after it in mapped host memory (the host waits on it)
 };

@@ -416,16 +416,19 @@ __device__ __forceinline__ float seg_min_256(const float* v, float* red) {
 // nzlist[256] | mean sequence [2T], then for the merge v[256] | scale[G] |
 // zb[G] | vp[2T] (update_lds_bytes).
 //
-// With kRegen (the update inside the rollout launch, where V is unchanged
-// until the merge) the chunk draws the controls of its samples of non-zero
-// weight again from the same Philox counters and the same V instead of
-// reading stored ones: sample_control is the function that drew them, so the
-// values are the same bits.  Stored controls would have been written by
-// workgroups on other XCDs, and each round of loads waits about 1.4 us for
-// memory after the device-scope acquire, while a redrawn control costs a few
-// tens of instructions; so the one-launch step stores no controls (except in
-// debug mode, for the debug view), and even a chunk whose every weight is
-// non-zero is summed sooner than by loading.
+// With kRegen the chunk draws the controls of its samples of non-zero
+// weight again from the same Philox counters and the same V (which the merge
+// rewrites only after every chunk is in) instead of reading stored ones:
+// sample_control is the function that drew them, so the values are the same
+// bits.  Stored controls would have been written by workgroups on other
+// XCDs, and each round of loads waits about 1.4 us for memory, while a
+// redrawn control costs a few tens of instructions; so a step stores no
+// controls unless the debug view or the gradient asks for them, and even a
+// chunk whose every weight is non-zero is summed sooner than by loading.
+// Where the controls are stored, the two-launch update reads them (the
+// one-launch update still draws them), so the bit-exact comparison of the
+// two forms in debug mode also checks that the drawn controls are the stored
+// ones.
 template <int kB, bool kRegen = false>
 __device__ __forceinline__ void update_chunk(const StepConst& c, int b, int parts, const float* __restrict__ S,
                                              const float* __restrict__ cvar, const float2* __restrict__ u,
@@ -970,7 +973,12 @@ __device__ __forceinline__ void update_body(const StepConst& c, int b, int G, in
                                             float* __restrict__ V, float* __restrict__ u0,
                                             float* __restrict__ u0_host, float* __restrict__ w_hat, float* ush,
                                             float* red, int* flag_sh, const GradOut* go = nullptr) {
-    update_chunk<16>(c, b, parts, S, cvar, u, S_tilde, part, ush, red);
+    // the stored controls when the rollouts stored them (debug and
+    // gradient modes), else the same controls drawn again
+    if (c.store_u)
+        update_chunk<16>(c, b, parts, S, cvar, u, S_tilde, part, ush, red);
+    else
+        update_chunk<16, true>(c, b, parts, S, cvar, u, S_tilde, part, ush, red, V);
     if (G == 1) {
         update_merge_single(c, part, S_tilde, V, u0, u0_host, w_hat, ush, red, go);
         return;

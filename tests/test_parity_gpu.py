@@ -315,25 +315,29 @@ def test_one_launch_step_equals_split_update(name, kw):
 
 @pytest.mark.parametrize("name,kw", [("c2", {}), ("c2", dict(lam=50.0)), ("c2", dict(lam=1.0e4, K=1000)),
                                      ("c1", dict(K=700, M=7, T=5, B=2.0, eta=0.3, lam=1.0e4))])
-def test_one_launch_step_without_stored_controls(name, kw):
-    # without the debug flag the one-launch step stores no sampled controls:
-    # its chunk updates draw the controls of the weighted samples again; V+
-    # and the first command equal those of the two-launch step (which stores
-    # and reads them), also when every weight is non-zero (large lambda)
+def test_steps_without_stored_controls(name, kw):
+    # without the debug flag no step stores its sampled controls: the chunk
+    # updates draw the controls of the weighted samples again; V+ and the
+    # first command of the one-launch and the two-launch step equal those of
+    # the two-launch step in debug mode (which stores the controls and reads
+    # them), also when every weight is non-zero (large lambda)
     p, obs, x0, _ = _world(name, **kw)
     p = dict(p, shift=True)
     V0 = W.random_V(p["T"], 5, scale=(1.0, 0.2))
     a = R.Controller(p, obs)
     b = R.Controller(p, obs, split_update=True)
-    Va, Vb = a.new_V(V0), b.new_V(V0)
+    c = R.Controller(p, obs, split_update=True, debug=True)
+    Va, Vb, Vc = a.new_V(V0), b.new_V(V0), c.new_V(V0)
     for j in range(3):
         ua = a.step(x0, Va, 11 + j, want_u0=True)
         ub = b.step(x0, Vb, 11 + j, want_u0=True)
+        uc = c.step(x0, Vc, 11 + j, want_u0=True)
         torch.cuda.synchronize()
-        assert np.array_equal(ua, ub), (j, ua, ub)
-        assert torch.equal(Va, Vb), j
+        assert np.array_equal(ua, uc) and np.array_equal(ub, uc), (j, ua, ub, uc)
+        assert torch.equal(Va, Vc) and torch.equal(Vb, Vc), j
     a.close()
     b.close()
+    c.close()
 
 
 @pytest.mark.parametrize("turns", [0, 17, -160])
