@@ -157,8 +157,9 @@ mppi_status mppi_create(const mppi_params *p, const float *obstacles_host,
  * Enqueues one kernel on `stream` when every workgroup of the step can be
  * resident on the device at once (the workgroups that finish a chunk of
  * samples then also run its update, and the last one the merge), else two
- * (rollouts, then the update); MPPI_F_SPLIT_UPDATE forces two.  Both give
- * the same bits. */
+ * (rollouts, then the update; for M > 256 three: rollouts over consecutive
+ * (sample, draw) pairs, the per-sample CVaR, the update);
+ * MPPI_F_SPLIT_UPDATE forces the latter.  All give the same bits. */
 mppi_status mppi_step(mppi_handle *h, const float x0[4], float *V_dev,
                       uint32_t step_idx, float *u0_host, void *stream);
 

@@ -238,6 +238,7 @@ void fill_static(ramppi::StepConst* cp, const mppi_params& p, const Geometry& g,
     c.flags = p.flags;
     c.debug = (p.flags & MPPI_F_DEBUG) != 0;
     c.store_u = c.debug;  // the update draws the controls it needs again
+    c.flat = 0;
 }
 
 // Per-launch constants that depend on the measured state and the call index
@@ -267,6 +268,7 @@ struct mppi_handle {
     float* u0_pinned_dev;  // its device address
     uint32_t u0_seq;       // last completion value requested
     bool fuse;             // one launch per step (the whole grid is resident at once)
+    bool flat;             // two launches with the flattened disturbed layout (M > 256)
     bool serving;          // a persistent serving launch is resident (mppi_serve_start)
     uint32_t serve_seq;    // last request posted in the session
     hipStream_t serve_stream;
@@ -473,6 +475,20 @@ mppi_status mppi_create(const mppi_params* p, const float* obstacles_host, void*
         fa.parts = ramppi::update_parts(p->T);
         if (e == hipSuccess) e = hipMemcpyAsync(h->ws + l.fuse, &fa, sizeof fa, hipMemcpyHostToDevice, s);
     }
+    // Two-launch steps whose samples need more than four waves (M > 256):
+    // the disturbed workgroups of five or more waves start only three to a
+    // compute unit at once, so their lanes are laid out instead as 256
+    // consecutive (sample, draw) pairs per workgroup (at most two samples,
+    // four waves) and each sample's CVaR is formed by a separate pass from
+    // the stored risk costs.  The gradient keeps the per-sample layout (its
+    // tail ranks come from the rollout's own CVaR pass).
+    h->flat = !h->fuse && p->M > 256 && !(p->flags & MPPI_F_GRAD);
+    if (h->flat) {
+        h->g.spb = 2;
+        h->g.block = 256;
+        h->g.n_nom_wg = (p->K + 255) / 256;
+        h->g.lds_rollout = rollout_lds_bytes(2, p);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipHostFree(h->u0_pinned);
@@ -509,6 +525,7 @@ mppi_status mppi_step(mppi_handle* h, const float x0[4], float* V_dev, uint32_t 
     ramppi::StepConst c;
     fill_static(&c, p, g, h->n_tail, h->n_warm);
     fill_dynamic(&c, p, x0, step_idx);
+    c.flat = h->flat;
 
     ramppi::StepBuffers bufs = step_buffers(h, V_dev);
     bufs.u0_host = u0_host ? h->u0_pinned_dev : nullptr;

@@ -217,6 +217,8 @@ struct StepConst {
     int32_t grad;        // record tail ranks for the gradient of the free energy
     int32_t store_u;     // store the sampled controls (debug view, gradient); without them
                          // the update draws the controls it needs again
+    int32_t flat;        // disturbed workgroups take blockDim consecutive (sample, draw)
+                         // pairs (at most spb samples) and store L; the CVaR is a separate pass
     uint32_t u0_seq;     // nonzero: after the first command, store this value to
                          // the word after it in mapped host memory (the host waits on it)
 };

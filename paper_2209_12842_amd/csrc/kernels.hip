@@ -181,6 +181,51 @@ __global__ void __launch_bounds__(1024) k_cvar(const float* __restrict__ L, int 
     if (active && m == 0) cvar_out[k] = cv;
 }
 
+// The CVaR pass of the flattened two-launch step (M > 256): one sample per
+// workgroup of P threads, P the power of two at or above M (at most 1024).
+// The M stored risk costs are scaled as cvar_epilogue scales them (the mean
+// summed by one thread in draw order), padded to P with -inf, sorted by the
+// same bitonic stages (larger first, equal costs by smaller draw index), and
+// the n_tail largest are summed in that order: the bits of cvar_epilogue,
+// whose ranks by counting would cost M comparisons per lane here.
+__global__ void __launch_bounds__(1024) k_cvar_sorted(const float* __restrict__ L, int M, int n_tail,
+                                                      int scale_risk, float B, float* __restrict__ cvar_out) {
+    extern __shared__ float srt[];
+    __shared__ float mean_sh;
+    const int P = (int)blockDim.x, tid = (int)threadIdx.x;
+    float* vals = srt;                              // P
+    int* ids = reinterpret_cast<int*>(srt + P);     // P
+    const float* Lk = L + (size_t)blockIdx.x * M;
+    float v = tid < M ? Lk[tid] : -__builtin_inff();
+    if (scale_risk) {
+        vals[tid] = v;
+        __syncthreads();
+        if (tid == 0) {
+            float s = 0.0f;
+            for (int j = 0; j < M; ++j) s += vals[j];
+            mean_sh = s / (float)M;
+        }
+        __syncthreads();
+        const float mu = mean_sh;
+        if (tid < M) v = __fmaf_rn(B, v - mu, mu);
+    }
+    int id = tid;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j >= 64; j >>= 1) {  // partner in another wave
+            __syncthreads();
+            vals[tid] = v;
+            ids[tid] = id;
+            __syncthreads();
+            bitonic_cx(v, id, vals[tid ^ j], ids[tid ^ j], tid, j, k);
+        }
+        bitonic_wave_stages(v, id, tid, k);
+    }
+    __syncthreads();
+    vals[tid] = v;
+    __syncthreads();
+    if (tid == 0) cvar_out[blockIdx.x] = tail_sum(vals, n_tail);
+}
+
 // ---- launchers ----
 
 template <bool kFuse>
@@ -257,7 +302,8 @@ size_t update_lds_bytes(int T, int G) {
 hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size_t lds_rollout, int G,
                        size_t lds_update, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_mid,
                        const FuseArgs* fa) {
-    const dim3 grid(c.n_nom_wg + (c.K + c.spb - 1) / c.spb);
+    const int64_t n_dist = c.flat ? ((int64_t)c.K * c.M + block - 1) / block : (c.K + c.spb - 1) / c.spb;
+    const dim3 grid((unsigned)(c.n_nom_wg + n_dist));
     if (ev_start) (void)hipEventRecord(ev_start, stream);
     if (fa) {  // one launch: the update runs in the workgroups that finish each chunk
         launch_rollout_t<true>(c, b, grid, block, lds_rollout > lds_update ? lds_rollout : lds_update, stream,
@@ -265,6 +311,12 @@ hipError_t launch_step(const StepConst& c, const StepBuffers& b, int block, size
         if (ev_mid) (void)hipEventRecord(ev_mid, stream);
     } else {
         launch_rollout_t<false>(c, b, grid, block, lds_rollout, stream, nullptr, nullptr, nullptr);
+        if (c.flat) {  // each sample's CVaR from the stored risk costs (one sample per workgroup)
+            int P = 64;
+            while (P < c.M) P <<= 1;
+            hipLaunchKernelGGL(k_cvar_sorted, dim3(c.K), dim3(P), 2 * sizeof(float) * (size_t)P, stream, b.L, c.M,
+                               c.n_tail, c.scale_risk, c.B, b.cvar);
+        }
         if (ev_mid) (void)hipEventRecord(ev_mid, stream);
         hipLaunchKernelGGL(k_update, dim3(G), dim3(256), lds_update, stream, c, G, update_parts(c.T), b.S, b.cvar,
                            b.u, b.S_tilde, b.part, b.counter, b.Vout, b.u0, b.u0_host, b.w_hat);

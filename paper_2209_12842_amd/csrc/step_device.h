@@ -261,10 +261,18 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     // nominal waves then finish a few microseconds after the disturbed ones.
     __builtin_amdgcn_s_setprio(2);
     const int wg = item - c.n_nom_wg;
-    for (int idx = tid; idx < spb * T; idx += blockDim.x) {
+    // The workgroup's samples: spb of them, or with c.flat the (at most spb)
+    // samples of its blockDim consecutive (sample, draw) pairs, k_first the
+    // first of them.
+    // (K M < 2^31 is checked on the host, so the pair indices fit 32 bits)
+    const uint32_t KM = (uint32_t)c.K * (uint32_t)M;
+    const uint32_t g0 = (uint32_t)wg * blockDim.x;  // flat: the first pair
+    const int k_first = c.flat ? (int)(g0 / (uint32_t)M) : wg * spb;
+    const int n_smp = c.flat ? (int)((min(g0 + blockDim.x, KM) - 1u) / (uint32_t)M) - k_first + 1 : spb;
+    for (int idx = tid; idx < n_smp * T; idx += blockDim.x) {
         const int sl = idx / T;
         const int t = idx - sl * T;
-        const int kk = wg * spb + sl;
+        const int kk = k_first + sl;
         float2 cu = make_float2(0.0f, 0.0f);
         if (kk < c.K) {
             const float2 u = sample_control(c, V, kk, t);
@@ -274,9 +282,17 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     }
     __syncthreads();
 
-    const int sl = tid / M;
-    const int m = tid - sl * M;
-    const int k = wg * spb + sl;
+    int sl, m, k;
+    if (c.flat) {  // lanes past the last pair repeat it, their results dropped
+        const uint32_t g = min(g0 + (uint32_t)tid, KM - 1u);
+        k = (int)(g / (uint32_t)M);
+        m = (int)(g - (uint32_t)k * (uint32_t)M);
+        sl = k - k_first;
+    } else {
+        sl = tid / M;
+        m = tid - sl * M;
+        k = wg * spb + sl;
+    }
     float L = 0.0f;
     {
         const StepConst cv = with_vector_constants(c);
@@ -285,7 +301,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
         // every lane runs a rollout (the obstacle test works on whole waves);
         // lanes past the workgroup's last sample repeat its controls, and the
         // results of inactive lanes are dropped
-        const float2* ck = ctl + min(sl, spb - 1) * T;
+        const float2* ck = ctl + min(sl, n_smp - 1) * T;
         const float4 e0 = n_grp > 0 ? otab[tid & 63] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         State s{0.0f, 0.0f, c.psi0, c.v0};
         float acc = 0.0f;
@@ -337,6 +353,21 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
             if (n_grp > 0) cnt += obstacle_hits_culled<kCullSteps>(otab, gbox, n_grp, e0, px, py, n, n_cand, n_gtest);
         }
         L = __fmaf_rn(c.c_obs, (float)cnt, acc);
+    }
+    if (c.flat) {
+        // the risk costs go to memory; a separate pass forms each sample's
+        // CVaR from them (k_cvar, the same epilogue); the pair index again
+        // from a copy of the thread index (see below)
+        int tid_f = tid;
+        asm volatile("" : "+v"(tid_f));
+        const uint32_t g = (uint32_t)wg * blockDim.x + (uint32_t)tid_f;
+        if (g < KM) L_out[g] = L;
+        if (work && (tid & 63) == 0) {
+            const int slot = (item * 16 + (tid >> 6)) & (kWorkSlots - 1);
+            atomicAdd(&work[slot], (unsigned long long)n_cand);
+            atomicAdd(&work[kWorkSlots + slot], (unsigned long long)n_gtest);
+        }
+        return;
     }
     // The lane's sample and draw again, from copies of the thread index and
     // of M that the compiler cannot tie to the ones above: the values derived

@@ -289,7 +289,12 @@ def test_dense_obstacle_fields(n_obs, M):
 
 
 @pytest.mark.parametrize("name,kw", [("c1", {}), ("c2", {}), ("p0", dict(M=128)), ("c1", dict(K=257, M=48, T=9)),
-                                     ("c1", dict(K=700, M=7, T=5, B=2.0, eta=0.3))])
+                                     ("c1", dict(K=700, M=7, T=5, B=2.0, eta=0.3)),
+                                     # M > 256: the two-launch step lays its disturbed lanes out as
+                                     # 256 consecutive (sample, draw) pairs per workgroup and forms
+                                     # the CVaR in a separate pass (ragged: 300 pairs per sample,
+                                     # and M = 512 with the sort of power-of-two M)
+                                     ("c1", dict(K=300, M=300)), ("c1", dict(K=129, M=512, T=12, B=2.0))])
 def test_one_launch_step_equals_split_update(name, kw):
     # the step as one launch (the update run by the workgroups that finish
     # each chunk) and as two launches give the same bits, over several calls
