@@ -48,6 +48,9 @@ CASES = [
     ("c2 shift", "c2", dict(), 3),
     ("smaller: K=300 T=17 M=24, 7 obstacles", "c1", dict(K=300, T=17, M=24, lam=20.0, shift=True), 4),
     ("c2 again", "c2", dict(), 5),
+    # M = 300: the handle's two-launch step takes the flattened layout, the
+    # no-alloc step the per-sample one; both give the same bits
+    ("paper shape: K=1024 T=30 M=300", "p0", dict(), 6),
 ]
 
 
