@@ -294,7 +294,8 @@ def test_dense_obstacle_fields(n_obs, M):
                                      # 256 consecutive (sample, draw) pairs per workgroup and forms
                                      # the CVaR in a separate pass (ragged: 300 pairs per sample,
                                      # and M = 512 with the sort of power-of-two M)
-                                     ("c1", dict(K=300, M=300)), ("c1", dict(K=129, M=512, T=12, B=2.0))])
+                                     ("c1", dict(K=300, M=300)), ("c1", dict(K=129, M=512, T=12, B=2.0)),
+                                     ("c1", dict(K=70, M=600, T=8, B=0.5))])
 def test_one_launch_step_equals_split_update(name, kw):
     # the step as one launch (the update run by the workgroups that finish
     # each chunk) and as two launches give the same bits, over several calls
