@@ -23,14 +23,14 @@
 namespace ramppi {
 
 // Workgroup order of the two-launch rollout kernel: the disturbed workgroups
-// first, the nominal ones last, so that where a grid is larger than what the
-// device holds at once the nominal workgroups are among the last to start
-// (the paper's K = 1024, M = 300 step: 1024 disturbed workgroups of five
-// waves and four nominal ones, of which 768 start at once; launch 72 ->
-// 67 us; the large step is unchanged).  The one-launch kernel keeps the
-// nominal workgroups first: they then start on compute units of their own
-// choosing rather than as the third workgroup of a unit (c2 about 1 us
-// shorter that way).
+// first, the nominal ones last, so that where a grid is a little larger than
+// what the device holds at once the workgroups that wait for a place are the
+// nominal ones, which take a fraction of a disturbed workgroup's time (the
+// paper's K = 1024, M = 300 step in its per-sample layout, of whose 1028
+// five-wave workgroups 768 start at once: launch 72 -> 67 us; the large step
+// is unchanged).  The one-launch kernel keeps the nominal workgroups first:
+// they then start on compute units of their own choosing rather than as the
+// third workgroup of a unit (c2 about 1 us shorter that way).
 __device__ __forceinline__ int rollout_item(const StepConst& c) {
     const int n_dist = (int)gridDim.x - c.n_nom_wg;
     const int b = (int)blockIdx.x;

@@ -356,7 +356,7 @@ __device__ __forceinline__ void rollout_body(const StepConst& c, const float4* _
     }
     if (c.flat) {
         // the risk costs go to memory; a separate pass forms each sample's
-        // CVaR from them (k_cvar, the same epilogue); the pair index again
+        // CVaR from them (k_cvar_sorted, the same order); the pair index again
         // from a copy of the thread index (see below)
         int tid_f = tid;
         asm volatile("" : "+v"(tid_f));
