@@ -31,7 +31,7 @@ import math
 import numpy as np
 
 # Settings shared by c1-c4 (the paper fixes none of these numbers for a
-# kinematic bicycle; they are this build's workload recipe).
+# kinematic bicycle; they are the synthetic workloads' own recipe).
 COMMON = dict(
     dt=0.05, wheelbase=2.5,
     u_lo=(-3.0, -0.5), u_hi=(3.0, 0.5),
